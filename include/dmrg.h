@@ -1,0 +1,209 @@
+/*
+ * dmrg.h -- C ABI of the MI355X two-site DMRG middle-site library
+ * (libdmrg_hip.so).
+ *
+ * The calls follow the paper's statement of one two-site DMRG sweep
+ * iteration (Zhai & Chan, "Low communication high performance ab initio
+ * density matrix renormalization group algorithms", Appendix A and B):
+ *
+ *   integrals           -> ab initio Hamiltonian (Appendix B, first equation),
+ *                          optionally one sub-Hamiltonian of the sum of
+ *                          sub-Hamiltonians (Section II.B)
+ *   dmrg_build_block    -> blocking (Appendix A, blocking formula) followed by
+ *                          transformation (Appendix A, operator transformation)
+ *                          site by site from an edge to the middle
+ *   dmrg_normal_to_complementary
+ *                       -> normal -> complementary transform of the mixed
+ *                          NC/CN partition (Section III.A)
+ *   dmrg_heff_create    -> blocking at the two dots and the list of sector
+ *                          products of H_eff (Section II.D/II.E, "list of GEMMs
+ *                          generated once for each site", Section II.G)
+ *   dmrg_heff_apply     -> H_eff psi (Appendix A, effective eigenproblem)
+ *   dmrg_davidson       -> Davidson solution of the effective eigenproblem
+ *   dmrg_renormalize    -> transformation of the blocked left operators into a
+ *                          new renormalized basis (Appendix A)
+ *
+ * Conventions shared with every caller:
+ *   spin-orbital p = 2*i + s (s = 0 alpha, 1 beta), spatial i = 0..K-1;
+ *   sector label (n_alpha, n_beta); site basis |0>,|a>,|b>,|ab>;
+ *   left block Lb = sites [0, KL), dots d1 = KL, d2 = KL+1, right block
+ *   Rb = [KL+2, K), KL = K/2 - 1 (K even);
+ *   a block grown by one site orders the rows of each enlarged sector by site
+ *   state (0, a, b, ab), each segment holding the old block's sector
+ *   q - q_site in the old block's order (sectors sorted by (n_alpha, n_beta));
+ *   wavefunction: sub-blocks (a, s1, s2, b), ordered by Lb sector a, then s1,
+ *   then s2 (b is fixed by the target); each m_a x m_b row-major.  n_vec
+ *   vectors are stored one after another (stride = dmrg_heff_dim).
+ *
+ * Memory: the library never allocates device memory.  The caller hands one
+ * device arena to dmrg_create; every operator, work list and Davidson vector
+ * is carved out of it.  Calls fail with DMRG_E_WORKSPACE when it is too small.
+ * Device pointers passed in (isometries, psi, sigma) stay owned by the caller.
+ *
+ * Errors: every call returns a dmrg_status; no exception or abort crosses the
+ * ABI.  Arguments are checked before any device work.  HIP errors map to
+ * DMRG_E_HIP with hipGetErrorString in dmrg_last_error().  Work is queued on
+ * the caller's stream (a hipStream_t passed as void*); asynchronous faults
+ * surface at the next synchronising call.  A context is not thread-safe.
+ */
+#ifndef DMRG_H
+#define DMRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dmrg_status;
+enum {
+    DMRG_OK = 0,
+    DMRG_E_ARG = -1,          /* invalid argument or shape */
+    DMRG_E_SYMMETRY = -2,     /* integrals break t_ij = t_ji or 8-fold v symmetry */
+    DMRG_E_WORKSPACE = -3,    /* arena too small */
+    DMRG_E_HIP = -4,          /* HIP runtime error */
+    DMRG_E_NONFINITE = -5,    /* NaN/Inf met in a Davidson vector */
+    DMRG_E_STATE = -6,        /* call out of order (e.g. no integrals) */
+    DMRG_E_UNSUPPORTED = -7   /* a sector larger than the kernels' 320-row limit */
+};
+
+enum { DMRG_LEFT = 0, DMRG_RIGHT = 1 };
+/* right-block schemes (left blocks are always NC: normal operators) */
+enum { DMRG_SCHEME_NC = 0,   /* complementary operators (P, Q, R) on the right */
+       DMRG_SCHEME_CN = 1 }; /* normal operators on the right, transformed at the middle */
+enum { DMRG_F64 = 0, DMRG_F32 = 1 };
+enum { DMRG_PREC_F64 = 0, DMRG_PREC_F32 = 1 };
+
+typedef struct dmrg_ctx dmrg_ctx;
+typedef struct dmrg_opset dmrg_opset;
+typedef struct dmrg_heff dmrg_heff;
+
+/* Block-sparse matrix with quantum-number-labelled sectors (a site
+ * isometry A[k] of the MPS, Appendix A).  Block b maps enlarged sector
+ * qn_row[2b..2b+1] (rows, enlarged basis order) to new sector
+ * qn_col[2b..2b+1]; for an isometry qn_row == qn_col.  Data is row-major
+ * rows[b] x cols[b] at element offset offset[b] of `data` (device, f64).
+ * The metadata arrays are host arrays, copied by the library. */
+typedef struct {
+    int32_t n_blocks;
+    const int32_t* qn_row;
+    const int32_t* qn_col;
+    const int64_t* rows;
+    const int64_t* cols;
+    const int64_t* offset;
+    int32_t dtype;
+    const void* data;
+} dmrg_bsm;
+
+typedef struct {
+    int32_t max_iter;         /* cap on iterations (matvec rounds) */
+    int32_t max_subspace;     /* vectors kept before a restart (>= 2*n_roots) */
+    double tol;               /* converged when every residual norm <= tol */
+    int32_t precision;        /* DMRG_PREC_F64, or DMRG_PREC_F32 for the mixed policy */
+    double switch_tol;        /* mixed policy: FP32 matvecs while max residual > switch_tol */
+    int32_t fixed_iters;      /* > 0: run exactly this many iterations (timing mode) */
+} dmrg_dav_opts;
+
+typedef struct {
+    int32_t iters;            /* iterations done */
+    int32_t matvecs;          /* H_eff psi products (vector count) */
+    int32_t matvecs_f32;      /* of which in FP32 */
+    int32_t converged;        /* 1 if every residual <= tol */
+    double max_residual;      /* final max residual norm */
+    double ms_total;          /* wall time of the call (device events) */
+    double ms_matvec;         /* time inside H_eff psi */
+} dmrg_dav_stats;
+
+const char* dmrg_status_string(dmrg_status s);
+/* thread-local detail of the last error */
+const char* dmrg_last_error(void);
+
+/* Context on HIP device `device` with the caller's device arena. */
+dmrg_status dmrg_create(dmrg_ctx** out, int32_t device, void* arena, int64_t arena_bytes);
+void dmrg_destroy(dmrg_ctx* ctx);
+/* bytes of the arena in use now / at peak */
+int64_t dmrg_arena_used(const dmrg_ctx* ctx);
+int64_t dmrg_arena_peak(const dmrg_ctx* ctx);
+
+/* Integrals of the ab initio Hamiltonian (Appendix B): h1e[K*K] and
+ * g2e[K^4] in chemists' order (ij|kl), host arrays (copied), e_core added to
+ * H_eff.  With n_proc > 1 the context keeps only sub-Hamiltonian proc_id
+ * (1-based) of the sum of sub-Hamiltonians (Section II.B, processor
+ * assignment with the NC rule): t_ij scaled by [proc(p,i)+proc(p,j)]/2 and
+ * v_ijkl kept when proc(p, sorted i,j,k,l) = 1.  Fails with DMRG_E_SYMMETRY
+ * if h is not symmetric or g not 8-fold symmetric to 1e-12. */
+dmrg_status dmrg_set_integrals(dmrg_ctx* ctx, int32_t K, int32_t n_elec, int32_t two_sz,
+                               const double* h1e, const double* g2e, double e_core,
+                               int32_t n_proc, int32_t proc_id);
+
+/* Edge-to-middle build: blocking then transformation for n_sites sites from
+ * the `side` edge (left: sites 0..n_sites-1; right: K-1 down to K-n_sites).
+ * isometries[j] is the isometry adding the j-th site counted from that edge.
+ * Left blocks hold normal operators; right blocks hold normal operators
+ * (DMRG_SCHEME_CN) or complementary ones (DMRG_SCHEME_NC).  The operator set
+ * lives in the context arena; free it with dmrg_opset_free. */
+dmrg_status dmrg_build_block(dmrg_ctx* ctx, int32_t side, int32_t n_sites,
+                             const dmrg_bsm* isometries, int32_t scheme,
+                             dmrg_opset** out, void* stream);
+
+/* Mixed NC/CN middle transform (Section III.A): replaces the two-index normal
+ * operators of a CN right block by the complementary P, Q of every pair of
+ * spin-orbitals to its left.  In place; cost O(K^4 M^2). */
+dmrg_status dmrg_normal_to_complementary(dmrg_ctx* ctx, dmrg_opset* right, void* stream);
+
+/* Blocking of the dots d1 (onto the left block) and d2 (onto the right
+ * block, which must hold complementary operators) and the work list of
+ * H_eff = sum over NC terms X^{L'} (x) Y^{R'}; built once, reused by every
+ * product.  n_roots sets the batch the FP32 copies and work lists serve. */
+dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right,
+                             int32_t n_roots, dmrg_heff** out, void* stream);
+int64_t dmrg_heff_dim(const dmrg_heff* H);
+
+/* sigma = H_eff psi for n_vec vectors (overwrite).  precision DMRG_PREC_F64:
+ * psi, sigma are double; DMRG_PREC_F32: float (operators rounded to binary32
+ * once, FP32 products with FP32 accumulation). */
+dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec,
+                            const void* psi, void* sigma, void* stream);
+
+/* diag[dim] (device, double) = diagonal of H_eff (Davidson preconditioner). */
+dmrg_status dmrg_heff_diag(dmrg_heff* H, double* diag, void* stream);
+
+/* Block Davidson for the n_roots lowest eigenpairs.  psi_io[n_roots*dim]
+ * (device, double): start vectors in, Ritz vectors out.  energies[n_roots]
+ * host out (e_core included).  Non-convergence is reported in stats, not as
+ * an error. */
+dmrg_status dmrg_davidson(dmrg_heff* H, int32_t n_roots, double* psi_io, double* energies,
+                          const dmrg_dav_opts* opts, dmrg_dav_stats* stats, void* stream);
+
+/* Transformation of the blocked L' = Lb + d1 operators through the isometry
+ * adding d1 (Appendix A, operator transformation): returns the left block of
+ * sites [0, KL+1) in the new renormalized basis. */
+dmrg_status dmrg_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_opset** out,
+                             void* stream);
+
+/* Algorithmic flops of one H_eff psi per vector (sum over terms of the
+ * cheaper multiplication order; identity and scalar factors cost 0), and the
+ * algorithmic HBM bytes of one product (operators once + psi + sigma). */
+int64_t dmrg_heff_flops(const dmrg_heff* H);
+int64_t dmrg_heff_bytes(const dmrg_heff* H, int32_t precision);
+/* number of H_eff terms (two-index, one-index, block Hamiltonians) */
+int32_t dmrg_heff_terms(const dmrg_heff* H, int32_t* n2, int32_t* n1, int32_t* nh);
+
+/* Sector metadata of an operator set's basis (host arrays of capacity
+ * >= n): returns the sector count; fills qn[2*i], dims[i] when non-null. */
+int32_t dmrg_opset_basis(const dmrg_opset* s, int32_t n, int32_t* qn, int64_t* dims);
+
+/* Operator-block readback for tests: copies block (bra sector, ket sector)
+ * of the operator named (kind, p, q) into host memory (row-major).  kind:
+ * 'H', 'C' (a+_p), 'A' (a+_p a+_q, p<q), 'B' (a+_p a_q), 'R' (R_p), 'Q' (Q_pq),
+ * 'D' (P_pq^+, p<q).  Returns DMRG_E_ARG if the operator or block is absent. */
+dmrg_status dmrg_opset_block(const dmrg_opset* s, char kind, int32_t p, int32_t q,
+                             const int32_t* qn_ket, double* out, int64_t out_elems);
+
+void dmrg_opset_free(dmrg_opset* s);
+void dmrg_heff_free(dmrg_heff* H);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,625 @@
+// Host core of the DMRG library: status handling, arena, operator-set
+// layout, site operators, isometry layout, work lists, weighted sums.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "core.hpp"
+
+namespace dmrg {
+static thread_local std::string g_last_error;
+}
+
+extern "C" const char* dmrg_last_error(void) { return dmrg::g_last_error.c_str(); }
+
+namespace dmrg {
+
+const QN kSiteQ[4] = {QN(0, 0), QN(1, 0), QN(0, 1), QN(1, 1)};
+
+dmrg_status fail(dmrg_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+dmrg_status hip_fail(int err, const char* where) {
+    g_last_error = std::string(where) + ": " + hipGetErrorString((hipError_t)err);
+    return DMRG_E_HIP;
+}
+
+int Basis::find(const QN& x) const {
+    auto it = std::lower_bound(q.begin(), q.end(), x);
+    if (it == q.end() || !(*it == x)) return -1;
+    return (int)(it - q.begin());
+}
+
+int OpSetImpl::skel_for(const QN& dq) {
+    for (size_t i = 0; i < skels.size(); ++i)
+        if (skels[i].dq == dq) return (int)i;
+    Skel s;
+    s.dq = dq;
+    s.blk_of_ket.assign(basis.size(), -1);
+    int64_t off = 0;
+    for (int k = 0; k < basis.size(); ++k) {
+        const int b = basis.find(basis.q[k] + dq);
+        if (b < 0) continue;
+        s.blk_of_ket[k] = (int)s.ket.size();
+        s.ket.push_back(k);
+        s.bra.push_back(b);
+        s.off.push_back(off);
+        off += (int64_t)basis.m[b] * basis.m[k];
+    }
+    s.size = off;
+    skels.push_back(std::move(s));
+    return (int)skels.size() - 1;
+}
+
+int OpSetImpl::family(char kind, const QN& dq, int par) {
+    for (size_t i = 0; i < fams.size(); ++i)
+        if (fams[i].kind == kind && fams[i].dq == dq) return (int)i;
+    Family f;
+    f.kind = kind;
+    f.dq = dq;
+    f.par = par;
+    f.skel = skel_for(dq);
+    fams.push_back(std::move(f));
+    return (int)fams.size() - 1;
+}
+
+int OpSetImpl::add_op(char kind, int p, int q, const QN& dq, int par) {
+    const int64_t key = okey(kind, p, q);
+    auto it = lookup.find(key);
+    if (it != lookup.end()) return it->second.first;
+    const int f = family(kind, dq, par);
+    Family& F = fams[f];
+    const int idx = (int)F.keys.size();
+    F.keys.push_back(key);
+    F.index[key] = idx;
+    lookup[key] = {f, idx};
+    return f;
+}
+
+void OpSetImpl::layout() {
+    int64_t off = 0;
+    for (auto& F : fams) {
+        F.stride = skels[F.skel].size;
+        F.base = off;
+        off += F.stride * (int64_t)F.keys.size();
+        off = (off + 31) & ~int64_t(31);   // 256-byte alignment of every family
+    }
+    elems = off;
+}
+
+// ---------------------------------------------------------------------------
+void Arena::init(void* p, int64_t n) {
+    base = (char*)p;
+    bytes = n;
+    free_.clear();
+    live_.clear();
+    // align the usable start to 256 bytes
+    const int64_t start = (int64_t)((256 - ((uintptr_t)p & 255)) & 255);
+    if (n > start) free_[start] = n - start;
+    used = peak = 0;
+}
+
+int64_t Arena::alloc(int64_t n) {
+    if (n <= 0) n = 256;
+    n = (n + 255) & ~int64_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= n) {
+            const int64_t off = it->first, sz = it->second;
+            free_.erase(it);
+            if (sz > n) free_[off + n] = sz - n;
+            live_[off] = n;
+            used += n;
+            peak = std::max(peak, used);
+            return off;
+        }
+    }
+    return -1;
+}
+
+void Arena::release(int64_t off) {
+    auto it = live_.find(off);
+    if (it == live_.end()) return;
+    int64_t o = off, n = it->second;
+    live_.erase(it);
+    used -= n;
+    auto nx = free_.lower_bound(o);
+    if (nx != free_.end() && o + n == nx->first) {
+        n += nx->second;
+        free_.erase(nx);
+    }
+    auto pv = free_.lower_bound(o);
+    if (pv != free_.begin()) {
+        --pv;
+        if (pv->first + pv->second == o) {
+            o = pv->first;
+            n += pv->second;
+            free_.erase(pv);
+        }
+    }
+    free_[o] = n;
+}
+
+dmrg_status alloc_set(Ctx* ctx, OpSetImpl& s) {
+    s.layout();
+    const int64_t off = ctx->arena.alloc(std::max<int64_t>(s.elems, 1) * 8);
+    if (off < 0)
+        return fail(DMRG_E_WORKSPACE, "arena too small for an operator set of " +
+                                          std::to_string(s.elems * 8) + " bytes");
+    s.region = off;
+    s.dev = (double*)(ctx->arena.base + off);
+    return DMRG_OK;
+}
+
+void free_set(Ctx* ctx, OpSetImpl& s) {
+    if (s.region >= 0) ctx->arena.release(s.region);
+    s.region = -1;
+    s.dev = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+QN Ref::dq() const {
+    if (type == 0) return QN(0, 0);
+    const QN d = set->fams[fam].dq;
+    return trans ? -d : d;
+}
+
+int Ref::par() const { return type == 0 ? 0 : set->fams[fam].par; }
+
+bool Ref::block(int k, int& bra, int64_t& off, int& ld, bool& tr) const {
+    if (type == 0) {
+        bra = k;
+        off = -1;
+        ld = 0;
+        tr = false;
+        return true;
+    }
+    const Family& F = set->fams[fam];
+    const Skel& S = set->skels[F.skel];
+    const Basis& B = set->basis;
+    if (!trans) {
+        const int b = S.blk_of_ket[k];
+        if (b < 0) return false;
+        bra = S.bra[b];
+        off = F.base + (int64_t)idx * F.stride + S.off[b];
+        ld = B.m[k];
+        tr = false;
+        return true;
+    }
+    const int k2 = B.find(B.q[k] - F.dq);
+    if (k2 < 0) return false;
+    const int b = S.blk_of_ket[k2];
+    if (b < 0) return false;
+    bra = k2;
+    off = F.base + (int64_t)idx * F.stride + S.off[b];
+    ld = B.m[k2];
+    tr = true;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+M4 M4::operator*(const M4& o) const {
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double s = 0;
+            for (int k = 0; k < 4; ++k) s += a[i][k] * o.a[k][j];
+            r.a[i][j] = s;
+        }
+    return r;
+}
+M4 M4::operator+(const M4& o) const {
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) r.a[i][j] = a[i][j] + o.a[i][j];
+    return r;
+}
+M4 M4::operator*(double s) const {
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) r.a[i][j] = a[i][j] * s;
+    return r;
+}
+M4 M4::T() const {
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) r.a[i][j] = a[j][i];
+    return r;
+}
+bool M4::zero() const {
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            if (a[i][j] != 0.0) return false;
+    return true;
+}
+
+static int proc1(int p, int i, int P) { return ((i - p) % P + P) % P == 0; }
+static int proc2(int p, int i, int j, int P) {
+    if (i > j) std::swap(i, j);
+    const long long x = (long long)(j - 1) * j / 2 + i - p;
+    return ((x % P) + P) % P == 0;
+}
+
+bool Ctx::pair_needed(int i, int j) const {
+    if (n_proc <= 1) return true;
+    return proc2(proc_id, i + 1, j + 1, n_proc) != 0;
+}
+
+M4 Ctx::c(int p) const {
+    M4 r;
+    if ((p & 1) == 0) {          // alpha: |0> -> |a>, |b> -> |ab>
+        r.a[1][0] = 1.0;
+        r.a[3][2] = 1.0;
+    } else {                     // beta: |0> -> |b>, |a> -> -|ab>
+        r.a[2][0] = 1.0;
+        r.a[3][1] = -1.0;
+    }
+    return r;
+}
+
+M4 Ctx::site_H(int n) const {
+    M4 r;
+    const int o[2] = {2 * n, 2 * n + 1};
+    for (int p : o)
+        for (int q : o) {
+            const double tt = t(p, q);
+            if (tt != 0.0) r = r + c(p) * c(q).T() * tt;
+            for (int rr : o)
+                for (int s : o) {
+                    const double vv = v(p, q, rr, s);
+                    if (vv != 0.0) r = r + c(p) * c(rr) * c(s).T() * c(q).T() * (0.5 * vv);
+                }
+        }
+    return r;
+}
+
+M4 Ctx::site_R(int n, int p) const {
+    M4 r;
+    const int o[2] = {2 * n, 2 * n + 1};
+    for (int q : o) {
+        const double tt = t(p, q);
+        if (tt != 0.0) r = r + c(q).T() * (0.5 * tt);
+        for (int rr : o)
+            for (int s : o) {
+                const double vv = v(p, q, rr, s);
+                if (vv != 0.0) r = r + c(rr) * c(s).T() * c(q).T() * vv;
+            }
+    }
+    return r;
+}
+
+M4 Ctx::site_Pd(int n, int p, int rr) const {
+    M4 r;
+    const int o[2] = {2 * n, 2 * n + 1};
+    for (int q : o)
+        for (int s : o) {
+            const double vv = v(p, q, rr, s);
+            if (vv != 0.0) r = r + c(q) * c(s) * vv;   // (a_s a_q)^T = a+_q a+_s
+        }
+    return r;
+}
+
+M4 Ctx::site_Q(int n, int p, int q) const {
+    M4 r;
+    const int o[2] = {2 * n, 2 * n + 1};
+    for (int rr : o)
+        for (int s : o) {
+            const double vv = v(p, q, rr, s) - v(p, s, rr, q);
+            if (vv != 0.0) r = r + c(rr) * c(s).T() * vv;
+        }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+dmrg_status make_iso(const Basis& old, const dmrg_bsm* bsm, Iso& out) {
+    if (!bsm || bsm->n_blocks <= 0 || !bsm->qn_col || !bsm->rows || !bsm->cols || !bsm->offset ||
+        !bsm->data)
+        return fail(DMRG_E_ARG, "isometry descriptor incomplete");
+    if (bsm->dtype != DMRG_F64) return fail(DMRG_E_ARG, "isometries must be float64");
+    std::vector<std::pair<QN, int>> order;
+    for (int b = 0; b < bsm->n_blocks; ++b) order.push_back({QN(bsm->qn_col[2 * b], bsm->qn_col[2 * b + 1]), b});
+    std::sort(order.begin(), order.end(),
+              [](const std::pair<QN, int>& x, const std::pair<QN, int>& y) { return x.first < y.first; });
+    out.dev = (const double*)bsm->data;
+    out.nb = Basis();
+    out.off.clear();
+    out.d.clear();
+    out.seg.clear();
+    for (size_t i = 0; i < order.size(); ++i) {
+        const QN q = order[i].first;
+        const int b = order[i].second;
+        if (i > 0 && order[i - 1].first == q) return fail(DMRG_E_ARG, "duplicate isometry sector");
+        if (bsm->qn_row && (bsm->qn_row[2 * b] != q.a || bsm->qn_row[2 * b + 1] != q.b))
+            return fail(DMRG_E_ARG, "isometry block must map sector q to q");
+        std::array<int, 4> seg;
+        int d = 0;
+        for (int s = 0; s < 4; ++s) {
+            const int k = old.find(q - kSiteQ[s]);
+            if (k < 0) { seg[s] = -1; continue; }
+            seg[s] = d;
+            d += old.m[k];
+        }
+        const int64_t m = bsm->cols[b];
+        if (bsm->rows[b] != d)
+            return fail(DMRG_E_ARG, "isometry rows " + std::to_string(bsm->rows[b]) +
+                                        " != enlarged dimension " + std::to_string(d) + " of sector (" +
+                                        std::to_string(q.a) + "," + std::to_string(q.b) + ")");
+        if (m <= 0 || m > d) return fail(DMRG_E_ARG, "isometry columns out of range");
+        out.nb.q.push_back(q);
+        out.nb.m.push_back((int)m);
+        out.nb.total += m;
+        out.off.push_back(bsm->offset[b]);
+        out.d.push_back(d);
+        out.seg.push_back(seg);
+    }
+    return DMRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+void WorkList::clear() {
+    for (auto& t : task) t.clear();
+    groups.clear();
+    contribs.clear();
+}
+
+size_t WorkList::ntasks() const {
+    size_t n = 0;
+    for (auto& t : task) n += t.size();
+    return n;
+}
+
+int row_class(int rows) {
+    for (int c = 0; c < dmrgk::kNumClass; ++c)
+        if (rows <= dmrgk::kClassRows[c]) return c;
+    return -1;
+}
+
+void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int n, int g0, int g1,
+                      int maxrows, bool accumulate) {
+    if (m <= 0 || n <= 0) return;
+    int cls = row_class(std::max(m, maxrows));
+    if (cls < 0) cls = dmrgk::kNumClass - 1;   // caller checks limits beforehand
+    for (int col0 = 0; col0 < n; col0 += dmrgk::kTN) {
+        dmrgk::Task t;
+        t.c_off = c_off;
+        t.ldc = ldc;
+        t.m = m;
+        t.n = n;
+        t.col0 = col0;
+        t.g0 = g0;
+        t.g1 = g1;
+        t.cbuf = cbuf | (accumulate ? 256 : 0);
+        w.task[cls].push_back(t);
+    }
+}
+
+// Every element a task can touch must lie inside its buffer: checked on the
+// host before any work list reaches the device.
+dmrg_status validate_work(const WorkList& w, const int64_t* size) {
+    auto in = [&](int buf, int64_t first, int64_t last) {
+        return buf >= 0 && buf < dmrgk::kMaxBuf && first >= 0 && last < size[buf] && first <= last;
+    };
+    for (int cls = 0; cls < dmrgk::kNumClass; ++cls) {
+        const int cap = dmrgk::kClassRows[cls];
+        int lg0 = -1, lg1 = -1;
+        for (const dmrgk::Task& t : w.task[cls]) {
+            if (t.m > cap || t.m < 1 || t.n < 1 || t.col0 < 0 || t.col0 >= t.n || t.ldc < t.n)
+                return fail(DMRG_E_STATE, "work list: bad task shape");
+            if (!in(t.cbuf & 7, t.c_off, t.c_off + (int64_t)(t.m - 1) * t.ldc + t.n - 1))
+                return fail(DMRG_E_STATE, "work list: output out of bounds");
+            if (t.g0 == lg0 && t.g1 == lg1) continue;
+            lg0 = t.g0;
+            lg1 = t.g1;
+            if (t.g0 < 0 || t.g1 > (int)w.groups.size() || t.g0 > t.g1)
+                return fail(DMRG_E_STATE, "work list: bad group range");
+            for (int g = t.g0; g < t.g1; ++g) {
+                const dmrgk::Group& G = w.groups[g];
+                if (G.mu < 1 || G.mu > cap) return fail(DMRG_E_STATE, "work list: group rows exceed class");
+                if (!(G.flags & dmrgk::G_HAS_X) && G.xid_coef != 0.0 && G.mu != t.m)
+                    return fail(DMRG_E_STATE, "work list: identity X with mismatched rows");
+                if (G.flags & dmrgk::G_HAS_X) {
+                    const bool tr = G.flags & dmrgk::G_TRANS_X;
+                    const int64_t last = tr ? G.x_off + (int64_t)(G.mu - 1) * G.ldx + t.m - 1
+                                            : G.x_off + (int64_t)(t.m - 1) * G.ldx + G.mu - 1;
+                    if ((tr ? G.ldx < t.m : G.ldx < G.mu) || !in(G.flags & 7, G.x_off, last))
+                        return fail(DMRG_E_STATE, "work list: X operand out of bounds");
+                }
+                if (G.c0 < 0 || G.c1 > (int)w.contribs.size() || G.c0 > G.c1)
+                    return fail(DMRG_E_STATE, "work list: bad contribution range");
+                for (int c = G.c0; c < G.c1; ++c) {
+                    const dmrgk::Contrib& q = w.contribs[c];
+                    const bool ida = q.flags & dmrgk::F_ID_A, idb = q.flags & dmrgk::F_ID_B;
+                    const bool ta = q.flags & dmrgk::F_TRANS_A, tb = q.flags & dmrgk::F_TRANS_B;
+                    const int abuf = q.flags & 7, bbuf = (q.flags >> 3) & 7;
+                    if (ida && idb) continue;
+                    if (ida) {          // U += alpha B[0:mu, 0:n]
+                        const int64_t last = tb ? q.b_off + (int64_t)(t.n - 1) * q.ldb + G.mu - 1
+                                                : q.b_off + (int64_t)(G.mu - 1) * q.ldb + t.n - 1;
+                        if (!in(bbuf, q.b_off, last)) return fail(DMRG_E_STATE, "work list: B (A=I) out of bounds");
+                        continue;
+                    }
+                    if (idb) {          // U += alpha A[0:mu, 0:n]
+                        const int64_t last = ta ? q.a_off + (int64_t)(t.n - 1) * q.lda + G.mu - 1
+                                                : q.a_off + (int64_t)(G.mu - 1) * q.lda + t.n - 1;
+                        if (!in(abuf, q.a_off, last)) return fail(DMRG_E_STATE, "work list: A (B=I) out of bounds");
+                        continue;
+                    }
+                    if (q.k < 1) return fail(DMRG_E_STATE, "work list: empty contraction");
+                    const int64_t la = ta ? q.a_off + (int64_t)(q.k - 1) * q.lda + G.mu - 1
+                                          : q.a_off + (int64_t)(G.mu - 1) * q.lda + q.k - 1;
+                    const int64_t lb = tb ? q.b_off + (int64_t)(t.n - 1) * q.ldb + q.k - 1
+                                          : q.b_off + (int64_t)(q.k - 1) * q.ldb + t.n - 1;
+                    if (!in(abuf, q.a_off, la)) return fail(DMRG_E_STATE, "work list: A out of bounds");
+                    if (!in(bbuf, q.b_off, lb)) return fail(DMRG_E_STATE, "work list: B out of bounds");
+                }
+            }
+        }
+    }
+    return DMRG_OK;
+}
+
+dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
+    int64_t bytes = 0;
+    int64_t toff[dmrgk::kNumClass];
+    for (int c = 0; c < dmrgk::kNumClass; ++c) {
+        toff[c] = bytes;
+        bytes += ((int64_t)w.task[c].size() * sizeof(dmrgk::Task) + 255) & ~int64_t(255);
+    }
+    const int64_t goff = bytes;
+    bytes += ((int64_t)w.groups.size() * sizeof(dmrgk::Group) + 255) & ~int64_t(255);
+    const int64_t coff = bytes;
+    bytes += ((int64_t)w.contribs.size() * sizeof(dmrgk::Contrib) + 255) & ~int64_t(255);
+    const int64_t reg = ctx->arena.alloc(bytes);
+    if (reg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for a work list of " + std::to_string(bytes) + " bytes");
+    d.region = reg;
+    char* base = ctx->arena.base + reg;
+    hipStream_t s = (hipStream_t)stream;
+    for (int c = 0; c < dmrgk::kNumClass; ++c) {
+        d.task[c] = (dmrgk::Task*)(base + toff[c]);
+        d.ntask[c] = (int)w.task[c].size();
+        if (!w.task[c].empty())
+            DMRG_HIP(hipMemcpyAsync(d.task[c], w.task[c].data(), w.task[c].size() * sizeof(dmrgk::Task),
+                                    hipMemcpyHostToDevice, s));
+    }
+    d.groups = (dmrgk::Group*)(base + goff);
+    d.contribs = (dmrgk::Contrib*)(base + coff);
+    if (!w.groups.empty())
+        DMRG_HIP(hipMemcpyAsync(d.groups, w.groups.data(), w.groups.size() * sizeof(dmrgk::Group),
+                                hipMemcpyHostToDevice, s));
+    if (!w.contribs.empty())
+        DMRG_HIP(hipMemcpyAsync(d.contribs, w.contribs.data(), w.contribs.size() * sizeof(dmrgk::Contrib),
+                                hipMemcpyHostToDevice, s));
+    DMRG_HIP(hipStreamSynchronize(s));   // host vectors may be released after return
+    return DMRG_OK;
+}
+
+void free_work(Ctx* ctx, DevWork& d) {
+    if (d.region >= 0) ctx->arena.release(d.region);
+    d = DevWork();
+}
+
+dmrg_status run_work_f64(const DevWork& d, const dmrgk::Bases<double>& b, int nvec, void* stream) {
+    for (int c = dmrgk::kNumClass - 1; c >= 0; --c)
+        DMRG_HIP(dmrgk::launch_chain_f64(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec, stream));
+    return DMRG_OK;
+}
+
+dmrg_status run_work_f32(const DevWork& d, const dmrgk::Bases<float>& b, int nvec, void* stream) {
+    for (int c = dmrgk::kNumClass - 1; c >= 0; --c)
+        DMRG_HIP(dmrgk::launch_chain_f32(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec, stream));
+    return DMRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// integral-weighted sums: one dense GEMM per input family,
+//   out[n_req x stride] = W[n_req x n_ops] . family[n_ops x stride]
+void plan_wsums(const OpSetImpl& src, WSumPlan& plan, OpSetImpl& temps) {
+    std::map<int, std::vector<int>> by_fam;
+    for (size_t i = 0; i < plan.reqs.size(); ++i) by_fam[plan.reqs[i].fam].push_back((int)i);
+    plan.out.assign(plan.reqs.size(), {-1, -1});
+    for (auto& kv : by_fam) {
+        const Family& F = src.fams[kv.first];
+        Family T;                      // a fresh temporary family per input family
+        T.kind = 'T';
+        T.dq = F.dq;
+        T.par = F.par;
+        T.skel = temps.skel_for(F.dq);
+        temps.fams.push_back(T);
+        const int tf = (int)temps.fams.size() - 1;
+        for (int r : kv.second) {
+            Family& TF = temps.fams[tf];
+            const int idx = (int)TF.keys.size();
+            const int64_t key = okey('T', tf, idx);
+            TF.keys.push_back(key);
+            TF.index[key] = idx;
+            plan.out[r] = {tf, idx};
+        }
+    }
+}
+
+dmrg_status family_gemm(Ctx* ctx, const std::vector<double>& W, const OpSetImpl& src, int sf,
+                        const OpSetImpl& dst, int df, int row0, int nrows, void* stream) {
+    const Family& F = src.fams[sf];
+    const Family& D = dst.fams[df];
+    const int nin = (int)F.keys.size();
+    const int64_t stride = F.stride;
+    if (nrows <= 0 || stride == 0) return DMRG_OK;
+    if (D.stride != stride) return fail(DMRG_E_ARG, "family_gemm: skeleton mismatch");
+    if (stride > INT32_MAX) return fail(DMRG_E_UNSUPPORTED, "operator larger than 2^31 elements");
+    if ((int64_t)W.size() != (int64_t)nrows * nin) return fail(DMRG_E_ARG, "family_gemm: weight shape");
+    if (nin == 0) {
+        DMRG_HIP(hipMemsetAsync(dst.dev + D.base + (int64_t)row0 * stride, 0, (size_t)nrows * stride * 8,
+                                (hipStream_t)stream));
+        return DMRG_OK;
+    }
+    const int64_t wreg = ctx->arena.alloc((int64_t)W.size() * 8);
+    if (wreg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for integral weights");
+    double* wdev = (double*)(ctx->arena.base + wreg);
+    hipStream_t s = (hipStream_t)stream;
+    int e = (int)hipMemcpyAsync(wdev, W.data(), W.size() * 8, hipMemcpyHostToDevice, s);
+    if (e) { ctx->arena.release(wreg); return hip_fail(e, "weights upload"); }
+    WorkList wl;
+    for (int r0 = 0; r0 < nrows; r0 += 64) {
+        const int rows = std::min(64, nrows - r0);
+        const int g0 = (int)wl.groups.size();
+        dmrgk::Group g{};
+        g.xid_coef = 1.0;
+        g.mu = rows;
+        g.c0 = (int)wl.contribs.size();
+        dmrgk::Contrib c{};
+        c.a_off = (int64_t)r0 * nin;
+        c.lda = nin;
+        c.b_off = F.base;
+        c.ldb = (int)stride;
+        c.k = nin;
+        c.alpha = 1.0;
+        c.flags = 0 | (1 << 3);
+        wl.contribs.push_back(c);
+        g.c1 = (int)wl.contribs.size();
+        wl.groups.push_back(g);
+        emit_block_tasks(wl, 3, D.base + (int64_t)(row0 + r0) * stride, (int)stride, rows, (int)stride,
+                         g0, g0 + 1, rows);
+    }
+    int64_t sz[dmrgk::kMaxBuf] = {0};
+    sz[0] = (int64_t)W.size();
+    sz[1] = src.elems;
+    sz[3] = dst.elems;
+    DevWork dw;
+    dmrg_status st = validate_work(wl, sz);
+    if (st == DMRG_OK) st = upload_work(ctx, wl, dw, stream);
+    if (st != DMRG_OK) { ctx->arena.release(wreg); return st; }
+    dmrgk::Bases<double> b{};
+    b.p[0] = wdev;
+    b.p[1] = src.dev;
+    b.p[3] = dst.dev;
+    st = run_work_f64(dw, b, 1, stream);
+    if (st == DMRG_OK) {
+        e = (int)hipStreamSynchronize(s);
+        if (e) st = hip_fail(e, "family gemm");
+    }
+    free_work(ctx, dw);
+    ctx->arena.release(wreg);
+    return st;
+}
+
+dmrg_status exec_wsums(Ctx* ctx, const OpSetImpl& src, const WSumPlan& plan, const OpSetImpl& temps,
+                       void* stream) {
+    std::map<int, std::vector<int>> rows_of;   // temp family -> request ids ordered by idx
+    for (size_t i = 0; i < plan.reqs.size(); ++i) rows_of[plan.out[i].first].push_back((int)i);
+    for (auto& kv : rows_of) {
+        auto& v = kv.second;
+        std::sort(v.begin(), v.end(), [&](int x, int y) { return plan.out[x].second < plan.out[y].second; });
+        std::vector<double> W;
+        for (int r : v) W.insert(W.end(), plan.reqs[r].w.begin(), plan.reqs[r].w.end());
+        dmrg_status st = family_gemm(ctx, W, src, plan.reqs[v[0]].fam, temps, kv.first, 0, (int)v.size(), stream);
+        if (st != DMRG_OK) return st;
+    }
+    return DMRG_OK;
+}
+
+}  // namespace dmrg

@@ -1,0 +1,281 @@
+// Host-side data model of the DMRG library.
+//
+// Blocks and their renormalized operators (Appendix A of the paper):
+//  * Basis: sectors (n_alpha, n_beta), sorted, with their dimensions;
+//  * Skel: the block layout of every operator of one shift dq on a basis
+//    (blocks ket q -> bra q+dq, row-major, contiguous);
+//  * Family: operators of one kind and one shift, stored back to back
+//    (stride = skeleton size) so an integral-weighted sum over a family is a
+//    dense GEMM over the operator index;
+//  * OpSet: a block = basis + families, one contiguous arena region.
+//
+// Operators on a block grown by one site are kept delayed ("transition
+// form", the delayed contraction of the blocking step): a list of
+// components (site bra state, site ket state, reference to an old-block
+// operator or the identity, coefficient, parity flag), never materialised on
+// the enlarged basis.  Renormalization and H_eff consume this form directly.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dmrg.h"
+#include "kernels.hpp"
+
+namespace dmrg {
+
+struct QN {
+    int a = 0, b = 0;
+    QN() = default;
+    QN(int x, int y) : a(x), b(y) {}
+    QN operator+(const QN& o) const { return {a + o.a, b + o.b}; }
+    QN operator-(const QN& o) const { return {a - o.a, b - o.b}; }
+    QN operator-() const { return {-a, -b}; }
+    bool operator==(const QN& o) const { return a == o.a && b == o.b; }
+    bool operator!=(const QN& o) const { return !(*this == o); }
+    bool operator<(const QN& o) const { return a < o.a || (a == o.a && b < o.b); }
+    int n() const { return a + b; }
+};
+
+// one-electron quantum number of spin-orbital p
+inline QN qe(int p) { return (p & 1) ? QN(0, 1) : QN(1, 0); }
+extern const QN kSiteQ[4];    // |0>, |a>, |b>, |ab>
+
+struct Basis {
+    std::vector<QN> q;
+    std::vector<int> m;
+    int64_t total = 0;
+    int find(const QN& x) const;
+    int size() const { return (int)q.size(); }
+};
+
+struct Skel {
+    QN dq;
+    std::vector<int> ket, bra;     // per block
+    std::vector<int64_t> off;      // element offset of block within one operator
+    std::vector<int> blk_of_ket;   // ket sector -> block index or -1
+    int64_t size = 0;
+};
+
+struct Family {
+    char kind;          // 'H','C','A','B','R','D'(P^+),'Q','T'(temporary)
+    QN dq;
+    int par = 0;
+    int skel = 0;
+    std::vector<int64_t> keys;
+    std::unordered_map<int64_t, int> index;
+    int64_t base = 0;   // element offset (within the set's region) of operator 0
+    int64_t stride = 0;
+};
+
+inline int64_t okey(char kind, int p, int q) {
+    return ((int64_t)(unsigned char)kind << 40) | ((int64_t)(p + 1) << 20) | (int64_t)(q + 1);
+}
+
+// element offsets are in units of double within the set region
+struct OpSetImpl {
+    Basis basis;
+    std::vector<Skel> skels;
+    std::vector<Family> fams;
+    std::unordered_map<int64_t, std::pair<int, int>> lookup;   // key -> (fam, idx)
+    std::vector<int> orbs;     // spin-orbitals of the block (increasing)
+    int side = 0;              // DMRG_LEFT / DMRG_RIGHT
+    int kind = 0;              // 0 normal, 1 complementary, 2 temporaries
+    int nsites = 0;
+    int64_t region = -1;       // arena byte offset
+    int64_t elems = 0;         // doubles in the region
+    double* dev = nullptr;     // device pointer of the region
+
+    int skel_for(const QN& dq);
+    int family(char kind, const QN& dq, int par);
+    int add_op(char kind, int p, int q, const QN& dq, int par);
+    void layout();             // assign bases/strides, elems
+    bool has(char kind, int p, int q) const { return lookup.count(okey(kind, p, q)) != 0; }
+};
+
+// device arena (caller-owned memory), first-fit allocator
+struct Arena {
+    char* base = nullptr;
+    int64_t bytes = 0;
+    std::map<int64_t, int64_t> free_;   // offset -> size
+    std::map<int64_t, int64_t> live_;
+    int64_t used = 0, peak = 0;
+    void init(void* p, int64_t n);
+    int64_t alloc(int64_t n);           // -1 on failure
+    void release(int64_t off);
+};
+
+struct Ctx;
+
+// reference to a block operator used as a component
+struct Ref {
+    int type = 0;                  // 0 identity, 1 operator
+    const OpSetImpl* set = nullptr;
+    int fam = -1, idx = -1;
+    bool trans = false;
+    QN dq() const;                 // shift of the referenced (possibly transposed) operator
+    int par() const;
+    // block with ket sector k: returns false if absent.  bra sector, offset
+    // (elements within the set region), leading dimension, transposed flag.
+    bool block(int k, int& bra, int64_t& off, int& ld, bool& tr) const;
+};
+
+struct Comp {
+    int sb, sk;          // site bra / ket state (0..3)
+    Ref ref;
+    double coef;
+    int sgn_par;         // multiply by (-1)^{n(ket block sector)} when 1
+};
+
+struct TransOp {
+    QN dq;               // total shift on the enlarged space
+    int par = 0;
+    std::vector<Comp> comps;
+};
+
+// 4x4 site matrices (row = bra state)
+struct M4 {
+    double a[4][4] = {{0}};
+    M4 operator*(const M4& o) const;
+    M4 operator+(const M4& o) const;
+    M4 operator*(double s) const;
+    M4 T() const;
+    bool zero() const;
+};
+
+struct Ctx {
+    int device = 0;
+    Arena arena;
+    bool has_ints = false;
+    int K = 0, na = 0, nb = 0;
+    double e_core = 0.0;
+    int n_proc = 1, proc_id = 1;
+    std::vector<double> h, g;     // masked spatial integrals
+    double t(int p, int q) const {
+        if ((p & 1) != (q & 1)) return 0.0;
+        return h[(size_t)(p >> 1) * K + (q >> 1)];
+    }
+    double v(int p, int q, int r, int s) const {
+        if ((p & 1) != (q & 1) || (r & 1) != (s & 1)) return 0.0;
+        const size_t K1 = K;
+        return g[(((size_t)(p >> 1) * K1 + (q >> 1)) * K1 + (r >> 1)) * K1 + (s >> 1)];
+    }
+    // spatial pair (i, j) kept by this sub-Hamiltonian (always true for n_proc == 1)
+    bool pair_needed(int i, int j) const;
+    // site operators of spatial orbital n
+    M4 c(int p) const;            // a+_p on its site
+    M4 site_H(int n) const;
+    M4 site_R(int n, int p) const;
+    M4 site_Pd(int n, int p, int r) const;   // P_pr^+ restricted to the site
+    M4 site_Q(int n, int p, int q) const;
+};
+
+// status helpers
+dmrg_status fail(dmrg_status s, const std::string& msg);
+dmrg_status hip_fail(int err, const char* where);
+#define DMRG_HIP(call)                                              \
+    do {                                                            \
+        int _e = (int)(call);                                       \
+        if (_e != 0) return ::dmrg::hip_fail(_e, #call);            \
+    } while (0)
+
+// sector layout of an isometry (enlarged rows by site state then old sector)
+struct Iso {
+    const double* dev = nullptr;
+    Basis nb;                          // new basis
+    std::vector<int64_t> off;          // per new sector: element offset of U_q
+    std::vector<int> d;                // rows
+    std::vector<std::array<int, 4>> seg;   // row offset of segment s (-1 absent)
+};
+dmrg_status make_iso(const Basis& old, const dmrg_bsm* bsm, Iso& out);
+
+// allocate + lay out an opset region
+dmrg_status alloc_set(Ctx* ctx, OpSetImpl& s);
+void free_set(Ctx* ctx, OpSetImpl& s);
+
+// ------------- work lists ---------------------------------------------------
+struct WorkList {
+    std::vector<dmrgk::Task> task[dmrgk::kNumClass];
+    std::vector<dmrgk::Group> groups;
+    std::vector<dmrgk::Contrib> contribs;
+    void clear();
+    size_t ntasks() const;
+};
+
+// device copy of a work list (in the arena)
+struct DevWork {
+    int64_t region = -1;
+    dmrgk::Task* task[dmrgk::kNumClass] = {nullptr, nullptr, nullptr};
+    int ntask[dmrgk::kNumClass] = {0, 0, 0};
+    dmrgk::Group* groups = nullptr;
+    dmrgk::Contrib* contribs = nullptr;
+};
+dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
+// host-side bounds check of every operand of every task; size[b] = elements of buffer b
+dmrg_status validate_work(const WorkList& w, const int64_t* size);
+void free_work(Ctx* ctx, DevWork& d);
+int row_class(int rows);
+dmrg_status run_work_f64(const DevWork& d, const dmrgk::Bases<double>& b, int nvec, void* stream);
+dmrg_status run_work_f32(const DevWork& d, const dmrgk::Bases<float>& b, int nvec, void* stream);
+
+// emit the tasks of one output block (m x n at c_off) with the given group range
+void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int n, int g0, int g1,
+                      int maxrows, bool accumulate = false);
+
+// ------------- weighted sums ------------------------------------------------
+// out (family in `temps`) = sum_k w_k * ops[k] of input family `fam` in `src`
+struct WSumReq {
+    int fam;                      // input family (in src)
+    std::vector<double> w;        // weight per operator of the family
+    int out_idx = -1;             // index of the result in the temp family
+};
+struct WSumPlan {
+    std::vector<WSumReq> reqs;
+    std::vector<std::pair<int, int>> out;   // (temp family, idx) per request
+};
+// registers one output family per input family in `temps` (before alloc_set)
+void plan_wsums(const OpSetImpl& src, WSumPlan& plan, OpSetImpl& temps);
+// dst family df rows [row0, row0+nrows) = W[nrows x nin] . src family sf
+dmrg_status family_gemm(Ctx* ctx, const std::vector<double>& W, const OpSetImpl& src, int sf,
+                        const OpSetImpl& dst, int df, int row0, int nrows, void* stream);
+// runs the GEMMs once `temps` is allocated; synchronises the stream
+dmrg_status exec_wsums(Ctx* ctx, const OpSetImpl& src, const WSumPlan& plan, const OpSetImpl& temps,
+                       void* stream);
+
+// operators of a block grown by one site, in transition form
+struct Grown {
+    std::vector<int64_t> keys;
+    std::vector<TransOp> ops;
+    std::vector<char> kinds;
+    std::vector<std::pair<int, int>> idx;
+    void add(char kind, int p, int q, const QN& dq, int par, TransOp&& T) {
+        T.dq = dq;
+        T.par = par;
+        keys.push_back(okey(kind, p, q));
+        kinds.push_back(kind);
+        idx.push_back({p, q});
+        ops.push_back(std::move(T));
+    }
+};
+
+void grow_left(const Ctx* C, const OpSetImpl& X, int n, const std::vector<int>& outside, Grown& G);
+void grow_right_compl(const Ctx* C, const OpSetImpl& Y, int n, const std::vector<int>& before, Grown& G);
+void compact(std::vector<TransOp>& ops, const OpSetImpl& old, WSumPlan& plan);
+void resolve(std::vector<TransOp>& ops, const WSumPlan& plan, const OpSetImpl& temps);
+// transformation of grown operators (refs into old / temps) through an isometry
+dmrg_status renormalize_grown(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const dmrg_bsm* iso,
+                              const Grown& G, OpSetImpl& nw, void* stream);
+
+}  // namespace dmrg
+
+struct dmrg_heff;
+dmrg::Ctx* heff_ctx(const dmrg_heff* H);
+
+struct dmrg_ctx : dmrg::Ctx {};
+struct dmrg_opset : dmrg::OpSetImpl {
+    dmrg::Ctx* ctx = nullptr;
+};

@@ -1,0 +1,693 @@
+// The effective Hamiltonian of the two-site middle step (Appendix A,
+// effective eigenproblem) as a sum over the normal/complementary terms of the
+// left-right decomposition across L' = Lb + d1 | R' = d2 + Rb:
+//
+//   H_eff = H^{L'} 1 + 1 H^{R'} + sum_{p in L'} (C_p R^{R'}_p - D_p R^{R'}_p+)
+//         + sum_{p in R'} (R^{L'}_p+ D_p - R^{L'}_p C_p)
+//         + sum_{p<r in L'} (A_pr P^{R'}_pr + h.c.) + sum_{pq in L'} B_pq Q^{R'}_pq
+//
+// with sigma = sum_terms X (P^{pi(Y)} Psi) Y^T.  Each operator of L' and R'
+// stays delayed: per site transition, one block-level operator of Lb (Rb)
+// or the identity.  The work list ("list of GEMMs generated once for each
+// site", Section II.G) has one output tile per (psi sub-block, 32 columns);
+// its groups are (term, left transition) and its contributions the right
+// transitions, so each term runs as psi . Y^T summed in LDS, then X . (that).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <unordered_set>
+
+#include "core.hpp"
+
+namespace dmrg {
+
+}  // namespace dmrg
+
+using namespace dmrg;
+
+struct PsiBlock {
+    int a, s1, s2, b;
+    int ma, mb;
+    int64_t off;
+};
+
+struct Term {
+    double coef;
+    TransOp X, Y;
+    char kind;    // '2', '1', 'H'
+};
+
+struct dmrg_heff {
+    Ctx* ctx = nullptr;
+    const OpSetImpl* Lb = nullptr;
+    const OpSetImpl* Rb = nullptr;
+    OpSetImpl TL, TR, TML, TMR;
+    Grown GL, GR;
+    std::vector<PsiBlock> blocks;
+    std::vector<int> blk_index;    // (a*4 + s1)*4 + s2 -> block or -1
+    int64_t dim = 0;
+    int n_roots = 1;
+    DevWork work;
+    // diagonal
+    int64_t diag_region = -1;
+    dmrgk::DiagBlock* dblocks = nullptr;
+    dmrgk::DiagTerm* dterms = nullptr;
+    int n_dblocks = 0;
+    // fp32 mirrors of buffers 0,1,4..7
+    int64_t f32_region = -1;
+    float* f32[8] = {nullptr};
+    int64_t flops = 0;
+    int64_t op_bytes64 = 0;
+    int n2 = 0, n1 = 0, nh = 0;
+    size_t ntask = 0, ngroup = 0, ncontrib = 0;
+};
+
+namespace dmrg {
+
+static TransOp transpose_left(const TransOp& T) {
+    TransOp R;
+    R.dq = -T.dq;
+    R.par = T.par;
+    for (const Comp& c : T.comps) {
+        Comp d = c;
+        d.sb = c.sk;
+        d.sk = c.sb;
+        if (c.ref.type == 1) d.ref.trans = !c.ref.trans;
+        const int dn = c.ref.dq().n();
+        if (c.sgn_par && (dn & 1)) d.coef = -c.coef;
+        R.comps.push_back(d);
+    }
+    return R;
+}
+
+static TransOp transpose_right(const TransOp& T) {
+    TransOp R;
+    R.dq = -T.dq;
+    R.par = T.par;
+    for (const Comp& c : T.comps) {
+        Comp d = c;
+        d.sb = c.sk;
+        d.sk = c.sb;
+        if (c.ref.type == 1) d.ref.trans = !c.ref.trans;
+        R.comps.push_back(d);
+    }
+    return R;
+}
+
+static TransOp identity_op() {
+    TransOp T;
+    T.dq = QN(0, 0);
+    T.par = 0;
+    for (int s = 0; s < 4; ++s) T.comps.push_back(Comp{s, s, Ref(), 1.0, 0});
+    return T;
+}
+
+// Replace every site transition holding two or more non-identity components
+// by one operator of `out` (sum of the components, signs folded per block).
+static dmrg_status materialize(Ctx* C, std::vector<TransOp*> ops, const OpSetImpl& base, const OpSetImpl& temps,
+                               OpSetImpl& out, void* stream) {
+    struct Job { TransOp* T; std::vector<int> comps; int sb, sk; int fam, idx; QN dq; };
+    std::vector<Job> jobs;
+    out.basis = base.basis;
+    out.kind = 2;
+    for (TransOp* T : ops) {
+        std::map<std::pair<int, int>, std::vector<int>> by;
+        for (size_t i = 0; i < T->comps.size(); ++i)
+            if (T->comps[i].ref.type == 1) by[{T->comps[i].sb, T->comps[i].sk}].push_back((int)i);
+        for (auto& kv : by) {
+            if (kv.second.size() < 2) continue;
+            Job j;
+            j.T = T;
+            j.comps = kv.second;
+            j.sb = kv.first.first;
+            j.sk = kv.first.second;
+            j.dq = T->comps[kv.second[0]].ref.dq();
+            const int f = out.family('M', j.dq, T->comps[kv.second[0]].ref.par());
+            Family& F = out.fams[f];
+            j.fam = f;
+            j.idx = (int)F.keys.size();
+            const int64_t key = okey('M', (int)jobs.size(), -1);
+            F.keys.push_back(key);
+            F.index[key] = j.idx;
+            jobs.push_back(j);
+        }
+    }
+    if (jobs.empty()) return DMRG_OK;
+    dmrg_status st = alloc_set(C, out);
+    if (st != DMRG_OK) return st;
+    WorkList wl;
+    const Basis& B = base.basis;
+    for (const Job& j : jobs) {
+        const Family& F = out.fams[j.fam];
+        const Skel& S = out.skels[F.skel];
+        for (size_t b = 0; b < S.ket.size(); ++b) {
+            const int a = S.ket[b], a2 = S.bra[b];
+            const int g0 = (int)wl.groups.size();
+            dmrgk::Group g{};
+            g.xid_coef = 1.0;
+            g.mu = B.m[a2];
+            g.c0 = (int)wl.contribs.size();
+            for (int ci : j.comps) {
+                const Comp& cp = j.T->comps[ci];
+                int bra, ld;
+                int64_t off;
+                bool tr;
+                if (!cp.ref.block(a, bra, off, ld, tr) || bra != a2) continue;
+                const double sg = (cp.sgn_par && (B.q[a].n() & 1)) ? -1.0 : 1.0;
+                dmrgk::Contrib c{};
+                c.a_off = off;
+                c.lda = ld;
+                c.k = B.m[a];
+                c.alpha = cp.coef * sg;
+                c.flags = ((cp.ref.set == &base) ? 0 : 1) | (tr ? dmrgk::F_TRANS_A : 0) | dmrgk::F_ID_B;
+                wl.contribs.push_back(c);
+            }
+            g.c1 = (int)wl.contribs.size();
+            int ng = 0;
+            if (g.c1 > g.c0) { wl.groups.push_back(g); ng = 1; }
+            emit_block_tasks(wl, 3, F.base + (int64_t)j.idx * F.stride + S.off[b], B.m[a], B.m[a2], B.m[a], g0,
+                             g0 + ng, B.m[a2]);
+        }
+    }
+    int64_t sz[dmrgk::kMaxBuf] = {0};
+    sz[0] = base.elems;
+    sz[1] = temps.dev ? temps.elems : base.elems;
+    sz[3] = out.elems;
+    DevWork dw;
+    st = validate_work(wl, sz);
+    if (st == DMRG_OK) st = upload_work(C, wl, dw, stream);
+    if (st != DMRG_OK) return st;
+    dmrgk::Bases<double> bs{};
+    bs.p[0] = base.dev;
+    bs.p[1] = temps.dev ? temps.dev : base.dev;
+    bs.p[3] = out.dev;
+    st = run_work_f64(dw, bs, 1, stream);
+    if (st == DMRG_OK) {
+        const int e = (int)hipStreamSynchronize((hipStream_t)stream);
+        if (e) st = hip_fail(e, "materialize");
+    }
+    free_work(C, dw);
+    if (st != DMRG_OK) return st;
+    // rewrite the transitions
+    std::map<TransOp*, std::vector<const Job*>> per;
+    for (const Job& j : jobs) per[j.T].push_back(&j);
+    for (auto& kv : per) {
+        TransOp* T = kv.first;
+        std::vector<char> drop(T->comps.size(), 0);
+        std::vector<Comp> add;
+        for (const Job* j : kv.second) {
+            for (int ci : j->comps) drop[ci] = 1;
+            Comp c;
+            c.sb = j->sb;
+            c.sk = j->sk;
+            c.ref.type = 1;
+            c.ref.set = &out;
+            c.ref.fam = j->fam;
+            c.ref.idx = j->idx;
+            c.ref.trans = false;
+            c.coef = 1.0;
+            c.sgn_par = 0;
+            add.push_back(c);
+        }
+        std::vector<Comp> keep;
+        for (size_t i = 0; i < T->comps.size(); ++i)
+            if (!drop[i]) keep.push_back(T->comps[i]);
+        keep.insert(keep.end(), add.begin(), add.end());
+        T->comps.swap(keep);
+    }
+    return DMRG_OK;
+}
+
+static int buf_of(const dmrg_heff* H, const OpSetImpl* s) {
+    if (s == H->Lb) return 0;
+    if (s == H->Rb) return 1;
+    if (s == &H->TL) return 4;
+    if (s == &H->TR) return 5;
+    if (s == &H->TML) return 6;
+    if (s == &H->TMR) return 7;
+    return -1;
+}
+
+}  // namespace dmrg
+
+static dmrg_status build_heff(dmrg_heff* H, void* stream) {
+    Ctx* C = H->ctx;
+    const int K = C->K, KL = K / 2 - 1;
+    const OpSetImpl& Lb = *H->Lb;
+    const OpSetImpl& Rb = *H->Rb;
+    std::vector<int> lp, rp;
+    for (int p = 0; p < 2 * (KL + 1); ++p) lp.push_back(p);
+    for (int p = 2 * (KL + 1); p < 2 * K; ++p) rp.push_back(p);
+    grow_left(C, Lb, KL, rp, H->GL);
+    grow_right_compl(C, Rb, KL + 1, lp, H->GR);
+    // weighted sums of Lb / Rb operators
+    {
+        WSumPlan pl, pr;
+        compact(H->GL.ops, Lb, pl);
+        compact(H->GR.ops, Rb, pr);
+        H->TL.basis = Lb.basis;
+        H->TL.kind = 2;
+        H->TR.basis = Rb.basis;
+        H->TR.kind = 2;
+        plan_wsums(Lb, pl, H->TL);
+        plan_wsums(Rb, pr, H->TR);
+        dmrg_status st = alloc_set(C, H->TL);
+        if (st == DMRG_OK) st = alloc_set(C, H->TR);
+        if (st == DMRG_OK) st = exec_wsums(C, Lb, pl, H->TL, stream);
+        if (st == DMRG_OK) st = exec_wsums(C, Rb, pr, H->TR, stream);
+        if (st != DMRG_OK) return st;
+        resolve(H->GL.ops, pl, H->TL);
+        resolve(H->GR.ops, pr, H->TR);
+    }
+    // working copies of L'/R' operators for the terms (multi-component
+    // transitions of H and R materialised; GL itself stays for renormalization)
+    std::unordered_map<int64_t, TransOp> Lx, Rx;
+    for (size_t i = 0; i < H->GL.keys.size(); ++i) Lx[H->GL.keys[i]] = H->GL.ops[i];
+    for (size_t i = 0; i < H->GR.keys.size(); ++i) Rx[H->GR.keys[i]] = H->GR.ops[i];
+    {
+        std::vector<TransOp*> ml, mr;
+        for (auto& kv : Lx) ml.push_back(&kv.second);
+        for (auto& kv : Rx) mr.push_back(&kv.second);
+        dmrg_status st = materialize(C, ml, Lb, H->TL, H->TML, stream);
+        if (st == DMRG_OK) st = materialize(C, mr, Rb, H->TR, H->TMR, stream);
+        if (st != DMRG_OK) return st;
+    }
+    auto L = [&](char k, int p, int q) -> const TransOp* {
+        auto it = Lx.find(okey(k, p, q));
+        return it == Lx.end() ? nullptr : &it->second;
+    };
+    auto R = [&](char k, int p, int q) -> const TransOp* {
+        auto it = Rx.find(okey(k, p, q));
+        return it == Rx.end() ? nullptr : &it->second;
+    };
+    std::vector<Term> terms;
+    terms.push_back(Term{1.0, *L('H', -1, -1), identity_op(), 'H'});
+    terms.push_back(Term{1.0, identity_op(), *R('H', -1, -1), 'H'});
+    for (int p : lp) {
+        const TransOp *c = L('C', p, -1), *r = R('R', p, -1);
+        if (!c || !r) continue;
+        terms.push_back(Term{1.0, *c, *r, '1'});
+        terms.push_back(Term{-1.0, transpose_left(*c), transpose_right(*r), '1'});
+    }
+    for (int p : rp) {
+        const TransOp *r = L('R', p, -1), *c = R('C', p, -1);
+        if (!c || !r) continue;
+        terms.push_back(Term{1.0, transpose_left(*r), transpose_right(*c), '1'});
+        terms.push_back(Term{-1.0, *r, *c, '1'});
+    }
+    for (size_t i = 0; i < lp.size(); ++i)
+        for (size_t j = i + 1; j < lp.size(); ++j) {
+            const int p = lp[i], r = lp[j];
+            const TransOp *a = L('A', p, r), *d = R('D', p, r);
+            if (!a || !d) continue;
+            terms.push_back(Term{1.0, *a, transpose_right(*d), '2'});
+            terms.push_back(Term{1.0, transpose_left(*a), *d, '2'});
+        }
+    for (int p : lp)
+        for (int q : lp) {
+            const TransOp *b = L('B', p, q), *Q = R('Q', p, q);
+            if (!b || !Q) continue;
+            terms.push_back(Term{1.0, *b, *Q, '2'});
+        }
+    if (C->e_core != 0.0) terms.push_back(Term{C->e_core, identity_op(), identity_op(), 'H'});
+    for (const Term& t : terms) {
+        if (t.kind == '2') H->n2++;
+        else if (t.kind == '1') H->n1++;
+        else H->nh++;
+    }
+    // wavefunction layout
+    const Basis& lb = Lb.basis;
+    const Basis& rb = Rb.basis;
+    const QN tgt(C->na, C->nb);
+    H->blk_index.assign((size_t)lb.size() * 16, -1);
+    int64_t off = 0;
+    for (int a = 0; a < lb.size(); ++a)
+        for (int s1 = 0; s1 < 4; ++s1)
+            for (int s2 = 0; s2 < 4; ++s2) {
+                const int b = rb.find(tgt - lb.q[a] - kSiteQ[s1] - kSiteQ[s2]);
+                if (b < 0) continue;
+                H->blk_index[(a * 4 + s1) * 4 + s2] = (int)H->blocks.size();
+                H->blocks.push_back(PsiBlock{a, s1, s2, b, lb.m[a], rb.m[b], off});
+                off += (int64_t)lb.m[a] * rb.m[b];
+            }
+    H->dim = off;
+    for (int m : lb.m)
+        if (m > 320) return fail(DMRG_E_UNSUPPORTED, "left sector above 320");
+    for (int m : rb.m)
+        if (m > 320) return fail(DMRG_E_UNSUPPORTED, "right sector above 320");
+    // per term: components by bra site state
+    struct TI { std::vector<const Comp*> x[4], y[4]; int piY; };
+    std::vector<TI> ti(terms.size());
+    for (size_t t = 0; t < terms.size(); ++t) {
+        for (const Comp& c : terms[t].X.comps) ti[t].x[c.sb].push_back(&c);
+        for (const Comp& c : terms[t].Y.comps) ti[t].y[c.sb].push_back(&c);
+        ti[t].piY = terms[t].Y.par;
+    }
+    WorkList wl;
+    std::vector<double> lfx(terms.size(), 0.0), lfy(terms.size(), 0.0), rfx(terms.size(), 0.0),
+        rfy(terms.size(), 0.0);
+    std::vector<std::unordered_set<uint64_t>> lx_seen(terms.size()), ry_seen(terms.size());
+    std::vector<dmrgk::DiagBlock> dbl;
+    std::vector<dmrgk::DiagTerm> dtm;
+    std::unordered_set<int64_t> seen_ops;
+    int64_t op_bytes = 0;
+    auto note = [&](int buf, int64_t o, int64_t n) {
+        const int64_t key = ((int64_t)buf << 56) ^ o;
+        if (seen_ops.insert(key).second) op_bytes += n;
+    };
+    struct Src { const Comp* x = nullptr; double xid = 0.0; double xco = 0.0; int a = -1; int bra, ld; int64_t off; bool tr; };
+    for (size_t o = 0; o < H->blocks.size(); ++o) {
+        const PsiBlock& O = H->blocks[o];
+        const int g0 = (int)wl.groups.size();
+        int maxmu = 0;
+        dmrgk::DiagBlock db{};
+        db.off = O.off;
+        db.ma = O.ma;
+        db.mb = O.mb;
+        db.c0 = (int)dtm.size();
+        for (size_t t = 0; t < terms.size(); ++t) {
+            const auto& xs = ti[t].x[O.s1];
+            const auto& ys = ti[t].y[O.s2];
+            if (xs.empty() || ys.empty()) continue;
+            // sources (a, s1) of this output: one X operator and/or identity
+            Src src[4];
+            for (const Comp* xc : xs) {
+                int a, bra = 0, ld = 0;
+                int64_t off = 0;
+                bool tr = false;
+                if (xc->ref.type == 0) {
+                    a = O.a;
+                } else {
+                    a = lb.find(lb.q[O.a] - xc->ref.dq());
+                    if (a < 0 || !xc->ref.block(a, bra, off, ld, tr) || bra != O.a) continue;
+                }
+                const int s1 = xc->sk;
+                Src& S = src[s1];
+                if (S.a >= 0 && S.a != a) return fail(DMRG_E_STATE, "inconsistent left source");
+                S.a = a;
+                const int nas = lb.q[a].n() + kSiteQ[s1].n();
+                double xco = terms[t].coef * xc->coef;
+                if (xc->sgn_par && (lb.q[a].n() & 1)) xco = -xco;
+                if (ti[t].piY && (nas & 1)) xco = -xco;
+                if (xc->ref.type == 0) {
+                    S.xid += xco;
+                } else {
+                    if (S.x) return fail(DMRG_E_STATE, "two left operators on one transition");
+                    S.x = xc;
+                    S.xco = xco;
+                    S.bra = bra;
+                    S.ld = ld;
+                    S.off = off;
+                    S.tr = tr;
+                }
+            }
+            for (int s1 = 0; s1 < 4; ++s1) {
+                const Src& S = src[s1];
+                if (S.a < 0 || (!S.x && S.xid == 0.0)) continue;
+                const int a = S.a;
+                dmrgk::Group g{};
+                g.mu = lb.m[a];
+                g.c0 = (int)wl.contribs.size();
+                g.xid_coef = S.xid;
+                int xb = -1;
+                if (S.x) {
+                    xb = buf_of(H, S.x->ref.set);
+                    g.x_off = S.off;
+                    g.ldx = S.ld;
+                    g.x_coef = S.xco;
+                    g.flags = xb | dmrgk::G_HAS_X | (S.tr ? dmrgk::G_TRANS_X : 0);
+                }
+                double fy = 0.0;
+                for (const Comp* yc : ys) {
+                    int b, bb = 0, ldy = 0;
+                    int64_t yoff = 0;
+                    bool ytr = false;
+                    if (yc->ref.type == 0) {
+                        b = O.b;
+                    } else {
+                        b = rb.find(rb.q[O.b] - yc->ref.dq());
+                        if (b < 0 || !yc->ref.block(b, bb, yoff, ldy, ytr) || bb != O.b) continue;
+                    }
+                    const int s2 = yc->sk;
+                    const int bi = H->blk_index[(a * 4 + s1) * 4 + s2];
+                    if (bi < 0 || H->blocks[bi].b != b) continue;
+                    const PsiBlock& I = H->blocks[bi];
+                    dmrgk::Contrib c{};
+                    c.a_off = I.off;
+                    c.lda = I.mb;
+                    c.k = I.mb;
+                    c.alpha = yc->coef;
+                    c.flags = 2;
+                    const uint64_t yci = (uint64_t)(yc - terms[t].Y.comps.data());
+                    if (yc->ref.type == 0) {
+                        c.flags |= dmrgk::F_ID_B;
+                    } else {
+                        // B[k=b][n=b'] = Y[b'][b]
+                        const int yb = buf_of(H, yc->ref.set);
+                        c.b_off = yoff;
+                        c.ldb = ldy;
+                        c.flags |= (yb << 3) | (ytr ? 0 : dmrgk::F_TRANS_B);
+                        fy += 2.0 * I.ma * I.mb * O.mb;
+                        note(yb, yoff, (int64_t)O.mb * I.mb);
+                        if (ry_seen[t].insert((yci << 32) | (uint64_t)bi).second)
+                            rfy[t] += 2.0 * I.ma * I.mb * O.mb;
+                        lfy[t] += 2.0 * O.ma * I.mb * O.mb;
+                    }
+                    wl.contribs.push_back(c);
+                    if (S.x) {
+                        const uint64_t xci = (uint64_t)(S.x - terms[t].X.comps.data());
+                        if (lx_seen[t].insert((xci << 32) | (uint64_t)bi).second)
+                            lfx[t] += 2.0 * O.ma * I.ma * I.mb;
+                    }
+                    if (I.a == O.a && s1 == O.s1 && s2 == O.s2 && I.b == O.b) {
+                        dmrgk::DiagTerm d{};
+                        d.y_off = -1;
+                        if (yc->ref.type != 0) {
+                            d.y_off = yoff;
+                            d.ldy = ldy;
+                            d.ybuf = buf_of(H, yc->ref.set);
+                        }
+                        if (S.x) {
+                            d.coef = S.xco * yc->coef;
+                            d.x_off = S.off;
+                            d.ldx = S.ld;
+                            d.xbuf = xb;
+                            dtm.push_back(d);
+                        }
+                        if (S.xid != 0.0) {
+                            d.coef = S.xid * yc->coef;
+                            d.x_off = -1;
+                            dtm.push_back(d);
+                        }
+                    }
+                }
+                g.c1 = (int)wl.contribs.size();
+                if (g.c1 == g.c0) continue;
+                wl.groups.push_back(g);
+                maxmu = std::max(maxmu, g.mu);
+                (void)fy;
+                if (S.x) {
+                    rfx[t] += 2.0 * O.ma * lb.m[a] * O.mb;
+                    note(xb, S.off, (int64_t)O.ma * lb.m[a]);
+                }
+            }
+        }
+        db.c1 = (int)dtm.size();
+        dbl.push_back(db);
+        emit_block_tasks(wl, 3, O.off, O.mb, O.ma, O.mb, g0, (int)wl.groups.size(), maxmu);
+    }
+    std::vector<double> lf(terms.size()), rf(terms.size());
+    for (size_t t = 0; t < terms.size(); ++t) {
+        lf[t] = lfx[t] + lfy[t];
+        rf[t] = rfx[t] + rfy[t];
+    }
+    double F = 0.0;
+    for (size_t t = 0; t < terms.size(); ++t) F += std::min(lf[t], rf[t]);
+    H->flops = (int64_t)F;
+    H->op_bytes64 = op_bytes * 8;
+    H->ntask = wl.ntasks();
+    H->ngroup = wl.groups.size();
+    H->ncontrib = wl.contribs.size();
+    {
+        int64_t sz[dmrgk::kMaxBuf] = {0};
+        sz[0] = Lb.elems;
+        sz[1] = Rb.elems;
+        sz[2] = sz[3] = H->dim;
+        sz[4] = H->TL.elems;
+        sz[5] = H->TR.elems;
+        sz[6] = H->TML.elems;
+        sz[7] = H->TMR.elems;
+        dmrg_status vs = validate_work(wl, sz);
+        if (vs != DMRG_OK) return vs;
+        for (const auto& d : dtm) {
+            if (d.x_off >= 0 && (d.xbuf < 0 || d.xbuf >= 8 || d.x_off >= sz[d.xbuf])) return fail(DMRG_E_STATE, "diag X");
+            if (d.y_off >= 0 && (d.ybuf < 0 || d.ybuf >= 8 || d.y_off >= sz[d.ybuf])) return fail(DMRG_E_STATE, "diag Y");
+        }
+    }
+    dmrg_status st = upload_work(C, wl, H->work, stream);
+    if (st != DMRG_OK) return st;
+    // diagonal lists
+    {
+        const int64_t bytes = ((int64_t)dbl.size() * sizeof(dmrgk::DiagBlock) + 255) / 256 * 256 +
+                              (int64_t)std::max<size_t>(dtm.size(), 1) * sizeof(dmrgk::DiagTerm);
+        H->diag_region = C->arena.alloc(bytes);
+        if (H->diag_region < 0) return fail(DMRG_E_WORKSPACE, "arena too small for diagonal lists");
+        char* base = C->arena.base + H->diag_region;
+        H->dblocks = (dmrgk::DiagBlock*)base;
+        H->dterms = (dmrgk::DiagTerm*)(base + ((int64_t)dbl.size() * sizeof(dmrgk::DiagBlock) + 255) / 256 * 256);
+        H->n_dblocks = (int)dbl.size();
+        DMRG_HIP(hipMemcpy(H->dblocks, dbl.data(), dbl.size() * sizeof(dmrgk::DiagBlock), hipMemcpyHostToDevice));
+        if (!dtm.empty())
+            DMRG_HIP(hipMemcpy(H->dterms, dtm.data(), dtm.size() * sizeof(dmrgk::DiagTerm), hipMemcpyHostToDevice));
+    }
+    return DMRG_OK;
+}
+
+static dmrgk::Bases<double> bases64(const dmrg_heff* H) {
+    dmrgk::Bases<double> b{};
+    b.p[0] = H->Lb->dev;
+    b.p[1] = H->Rb->dev;
+    b.p[4] = H->TL.dev;
+    b.p[5] = H->TR.dev;
+    b.p[6] = H->TML.dev;
+    b.p[7] = H->TMR.dev;
+    for (int i = 0; i < 8; ++i)
+        if (!b.p[i]) b.p[i] = H->Lb->dev;
+    return b;
+}
+
+static dmrg_status ensure_f32(dmrg_heff* H, void* stream) {
+    if (H->f32_region >= 0) return DMRG_OK;
+    const OpSetImpl* sets[8] = {H->Lb, H->Rb, nullptr, nullptr, &H->TL, &H->TR, &H->TML, &H->TMR};
+    int64_t off[8] = {0};
+    int64_t total = 0;
+    for (int i = 0; i < 8; ++i) {
+        if (!sets[i] || !sets[i]->dev) continue;
+        off[i] = total;
+        total += (sets[i]->elems * 4 + 255) / 256 * 256;
+    }
+    H->f32_region = H->ctx->arena.alloc(std::max<int64_t>(total, 256));
+    if (H->f32_region < 0) return fail(DMRG_E_WORKSPACE, "arena too small for FP32 operator copies");
+    char* base = H->ctx->arena.base + H->f32_region;
+    for (int i = 0; i < 8; ++i) {
+        if (!sets[i] || !sets[i]->dev) continue;
+        H->f32[i] = (float*)(base + off[i]);
+        DMRG_HIP(dmrgk::launch_cast_d2f(sets[i]->dev, H->f32[i], sets[i]->elems, stream));
+    }
+    return DMRG_OK;
+}
+
+Ctx* heff_ctx(const dmrg_heff* H) { return H->ctx; }
+
+extern "C" {
+
+dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right, int32_t n_roots,
+                             dmrg_heff** out, void* stream) {
+    if (!ctx || !left || !right || !out) return fail(DMRG_E_ARG, "null argument");
+    *out = nullptr;
+    if (!ctx->has_ints) return fail(DMRG_E_STATE, "integrals not set");
+    const int K = ctx->K, KL = K / 2 - 1;
+    if (left->side != DMRG_LEFT || left->kind != 0 || left->nsites != KL)
+        return fail(DMRG_E_ARG, "left must be the normal left block of K/2-1 sites");
+    if (right->side != DMRG_RIGHT || right->kind != 1 || right->nsites != K - KL - 2)
+        return fail(DMRG_E_ARG, "right must be a complementary right block of K/2-1 sites");
+    if (n_roots < 1 || n_roots > 32) return fail(DMRG_E_ARG, "n_roots must be 1..32");
+    dmrg_heff* H = new dmrg_heff();
+    H->ctx = ctx;
+    H->Lb = left;
+    H->Rb = right;
+    H->n_roots = n_roots;
+    dmrg_status st = build_heff(H, stream);
+    if (st != DMRG_OK) {
+        dmrg_heff_free(H);
+        return st;
+    }
+    *out = H;
+    return DMRG_OK;
+}
+
+int64_t dmrg_heff_dim(const dmrg_heff* H) { return H ? H->dim : -1; }
+int64_t dmrg_heff_flops(const dmrg_heff* H) { return H ? H->flops : -1; }
+int64_t dmrg_heff_bytes(const dmrg_heff* H, int32_t precision) {
+    if (!H) return -1;
+    const int64_t es = precision == DMRG_PREC_F32 ? 4 : 8;
+    return H->op_bytes64 / 8 * es + 2 * H->dim * es;
+}
+int32_t dmrg_heff_terms(const dmrg_heff* H, int32_t* n2, int32_t* n1, int32_t* nh) {
+    if (!H) return -1;
+    if (n2) *n2 = H->n2;
+    if (n1) *n1 = H->n1;
+    if (nh) *nh = H->nh;
+    return H->n2 + H->n1 + H->nh;
+}
+
+dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec, const void* psi, void* sigma,
+                            void* stream) {
+    if (!H || !psi || !sigma) return fail(DMRG_E_ARG, "null argument");
+    if (n_vec < 1 || n_vec > 65535) return fail(DMRG_E_ARG, "bad n_vec");
+    if (psi == sigma) return fail(DMRG_E_ARG, "psi and sigma must not alias");
+    if (precision == DMRG_PREC_F64) {
+        dmrgk::Bases<double> b = bases64(H);
+        b.p[2] = (double*)psi;
+        b.p[3] = (double*)sigma;
+        b.vstride[2] = b.vstride[3] = H->dim;
+        return run_work_f64(H->work, b, n_vec, stream);
+    }
+    if (precision == DMRG_PREC_F32) {
+        dmrg_status st = ensure_f32(H, stream);
+        if (st != DMRG_OK) return st;
+        dmrgk::Bases<float> b{};
+        for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
+        b.p[2] = (float*)psi;
+        b.p[3] = (float*)sigma;
+        b.vstride[2] = b.vstride[3] = H->dim;
+        return run_work_f32(H->work, b, n_vec, stream);
+    }
+    return fail(DMRG_E_ARG, "bad precision");
+}
+
+dmrg_status dmrg_heff_diag(dmrg_heff* H, double* diag, void* stream) {
+    if (!H || !diag) return fail(DMRG_E_ARG, "null argument");
+    DMRG_HIP(dmrgk::launch_diag(H->dblocks, H->n_dblocks, H->dterms, bases64(H), diag, stream));
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_opset** out, void* stream) {
+    if (!H || !isometry || !out) return fail(DMRG_E_ARG, "null argument");
+    *out = nullptr;
+    dmrg_opset* o = new dmrg_opset();
+    o->side = DMRG_LEFT;
+    o->kind = 0;
+    dmrg_status st = renormalize_grown(H->ctx, *H->Lb, &H->TL, isometry, H->GL, *o, stream);
+    if (st != DMRG_OK) {
+        if (o->region >= 0) free_set(H->ctx, *o);
+        delete o;
+        return st;
+    }
+    o->orbs = H->Lb->orbs;
+    const int d1 = H->ctx->K / 2 - 1;
+    o->orbs.push_back(2 * d1);
+    o->orbs.push_back(2 * d1 + 1);
+    o->nsites = H->Lb->nsites + 1;
+    o->ctx = H->ctx;
+    *out = o;
+    return DMRG_OK;
+}
+
+void dmrg_heff_free(dmrg_heff* H) {
+    if (!H) return;
+    Ctx* C = H->ctx;
+    free_work(C, H->work);
+    free_set(C, H->TL);
+    free_set(C, H->TR);
+    free_set(C, H->TML);
+    free_set(C, H->TMR);
+    if (H->diag_region >= 0) C->arena.release(H->diag_region);
+    if (H->f32_region >= 0) C->arena.release(H->f32_region);
+    delete H;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Device work-list records and kernel launchers of the DMRG library.
+//
+// Everything heavy (blocking + transformation, the normal->complementary
+// transform, the integral-weighted operator sums and H_eff psi) is expressed
+// as one kind of work: an output tile C (rows x 32 columns of a sector
+// block) accumulated as
+//
+//     C = sum_groups [ x_coef * X_g . U_g + xid_coef * U_g ],
+//     U_g = sum_{c in g} alpha_c * A_c . B_c
+//
+// where every operand is a dense sector block in one of up to eight device
+// buffers, optionally transposed or an identity.  For H_eff psi, A_c is a
+// psi sub-block, B_c a right operator block (transposed) and X_g a left
+// operator block: the two products of one term run back to back with the
+// intermediate U_g staged in LDS (never written to HBM).  For the
+// transformation U^T O U, X_g = U^T, A_c = O (each component of the
+// blocked operator), B_c = U.  A plain GEMM is the case X = identity with a
+// single contribution.  Tiles are owned by exactly one workgroup and
+// contributions are summed in list order, so results are deterministic.
+#pragma once
+#include <cstdint>
+
+namespace dmrgk {
+
+constexpr int kTN = 32;          // output columns per task
+constexpr int kMaxBuf = 8;
+
+// flag bits
+enum : int32_t {
+    F_TRANS_A = 1 << 6, F_TRANS_B = 1 << 7, F_ID_A = 1 << 8, F_ID_B = 1 << 9,
+    G_TRANS_X = 1 << 3, G_HAS_X = 1 << 4,
+};
+
+struct Task {          // one output tile
+    int64_t c_off;     // element offset of the block in buffer cbuf
+    int32_t ldc, m, n; // block rows, columns (tile covers columns col0..col0+31)
+    int32_t col0;
+    int32_t g0, g1;    // group range
+    int32_t cbuf;      // buffer id of C | (accumulate << 8)
+};
+
+struct Group {
+    int64_t x_off;
+    double x_coef, xid_coef;
+    int32_t ldx, mu;   // mu = rows of U = inner dimension of X . U
+    int32_t flags;     // xbuf (bits 0-2) | G_TRANS_X | G_HAS_X
+    int32_t c0, c1;    // contribution range
+    int32_t pad;
+};
+
+struct Contrib {
+    int64_t a_off, b_off;
+    double alpha;
+    int32_t lda, ldb, k;
+    int32_t flags;     // abuf (0-2) | bbuf (3-5) | F_TRANS_A | F_TRANS_B | F_ID_A | F_ID_B
+};
+
+template <typename T>
+struct Bases {
+    T* p[kMaxBuf];
+    int64_t vstride[kMaxBuf];   // per-vector stride (batched vectors, grid.y)
+};
+
+// row classes: tasks whose rows (and U rows) fit 64, 128 or 320
+constexpr int kNumClass = 3;
+constexpr int kClassRows[kNumClass] = {64, 128, 320};
+
+// launchers (return hipError_t as int)
+int launch_chain_f64(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+                     const Bases<double>& b, int nvec, void* stream);
+int launch_chain_f32(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+                     const Bases<float>& b, int nvec, void* stream);
+
+int launch_cast_d2f(const double* in, float* out, int64_t n, void* stream);
+int launch_cast_f2d(const float* in, double* out, int64_t n, void* stream);
+
+// H_eff diagonal: for each psi sub-block o, diag[o](i,j) = sum over its
+// contributions (x_off, y_off, coef): coef * X[i,i] * Y[j,j] (X or Y < 0 => 1)
+struct DiagBlock { int64_t off; int32_t ma, mb; int32_t c0, c1; };
+struct DiagTerm { int64_t x_off, y_off; double coef; int32_t ldx, ldy; int32_t xbuf, ybuf; };
+int launch_diag(const DiagBlock* blocks, int nblock, const DiagTerm* terms, Bases<double> b,
+                double* diag, void* stream);
+
+// Davidson helpers (FP64)
+// G[i*ldg + j] = <V_i, W_j>, i < nv, j < nw; vectors of length n at strides
+int launch_gram(const double* V, int nv, const double* W, int nw, int64_t n,
+                double* G, int ldg, double* scratch, void* stream);
+// Y_j = sum_i C[i*ldc + j] V_i (+ beta Y_j) for j < ny
+int launch_combine(const double* V, int nv, const double* C, int ldc, double* Y, int ny,
+                   int64_t n, double beta, void* stream);
+// t = r / clamp(theta - d)   (preconditioned residual)
+int launch_precond(const double* r, const double* d, double theta, double* t, int64_t n,
+                   void* stream);
+// symmetric eigen-decomposition of an n x n matrix (n <= 64), one workgroup,
+// cyclic Jacobi; A row-major in, eigenvalues ascending in w, eigenvectors as
+// columns of Z (row-major n x n)
+int launch_jacobi(const double* A, int n, double* w, double* Z, void* stream);
+// count of non-finite entries -> *flag (int)
+int launch_nonfinite(const double* x, int64_t n, int* flag, void* stream);
+
+}  // namespace dmrgk
