@@ -390,6 +390,7 @@ void resolve(std::vector<TransOp>& ops, const WSumPlan& plan, const OpSetImpl& t
 static dmrg_status renormalize_ops(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const Iso& iso,
                                    const Grown& G, OpSetImpl& nw, void* stream) {
     nw.basis = iso.nb;
+    nw.basis.index();
     nw.skels.clear();
     nw.fams.clear();
     nw.lookup.clear();

@@ -30,10 +30,21 @@ dmrg_status hip_fail(int err, const char* where) {
     return DMRG_E_HIP;
 }
 
-int Basis::find(const QN& x) const {
+int Basis::find_slow(const QN& x) const {
     auto it = std::lower_bound(q.begin(), q.end(), x);
     if (it == q.end() || !(*it == x)) return -1;
     return (int)(it - q.begin());
+}
+
+void Basis::index() {
+    amax = bmax = 0;
+    for (const QN& x : q) {
+        amax = std::max(amax, x.a);
+        bmax = std::max(bmax, x.b);
+    }
+    tab.assign((size_t)(amax + 1) * (bmax + 1), -1);
+    for (size_t i = 0; i < q.size(); ++i)
+        if (q[i].a >= 0 && q[i].b >= 0) tab[(size_t)q[i].a * (bmax + 1) + q[i].b] = (int)i;
 }
 
 int OpSetImpl::skel_for(const QN& dq) {
@@ -146,6 +157,7 @@ void Arena::release(int64_t off) {
 }
 
 dmrg_status alloc_set(Ctx* ctx, OpSetImpl& s) {
+    if (s.basis.tab.empty()) s.basis.index();
     s.layout();
     const int64_t off = ctx->arena.alloc(std::max<int64_t>(s.elems, 1) * 8);
     if (off < 0)

@@ -49,7 +49,18 @@ struct Basis {
     std::vector<QN> q;
     std::vector<int> m;
     int64_t total = 0;
-    int find(const QN& x) const;
+    // O(1) sector lookup table over (n_alpha, n_beta), built by index()
+    std::vector<int> tab;
+    int amax = -1, bmax = -1;
+    int find(const QN& x) const {
+        if (!tab.empty()) {
+            if (x.a < 0 || x.b < 0 || x.a > amax || x.b > bmax) return -1;
+            return tab[(size_t)x.a * (bmax + 1) + x.b];
+        }
+        return find_slow(x);
+    }
+    int find_slow(const QN& x) const;
+    void index();
     int size() const { return (int)q.size(); }
 };
 

@@ -18,9 +18,25 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <thread>
 #include <unordered_set>
 
 #include "core.hpp"
+
+// per-phase host timing on stderr when DMRG_VERBOSE is set
+struct PhaseClock {
+    bool on = std::getenv("DMRG_VERBOSE") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void mark(const char* what) {
+        if (!on) return;
+        const auto n = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[dmrg] %-28s %8.3f s\n", what, std::chrono::duration<double>(n - t).count());
+        t = n;
+    }
+};
 
 namespace dmrg {
 
@@ -241,8 +257,10 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
     std::vector<int> lp, rp;
     for (int p = 0; p < 2 * (KL + 1); ++p) lp.push_back(p);
     for (int p = 2 * (KL + 1); p < 2 * K; ++p) rp.push_back(p);
+    PhaseClock clk;
     grow_left(C, Lb, KL, rp, H->GL);
     grow_right_compl(C, Rb, KL + 1, lp, H->GR);
+    clk.mark("grow L' R'");
     // weighted sums of Lb / Rb operators
     {
         WSumPlan pl, pr;
@@ -262,6 +280,7 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         resolve(H->GL.ops, pl, H->TL);
         resolve(H->GR.ops, pr, H->TR);
     }
+    clk.mark("weighted sums");
     // working copies of L'/R' operators for the terms (multi-component
     // transitions of H and R materialised; GL itself stays for renormalization)
     std::unordered_map<int64_t, TransOp> Lx, Rx;
@@ -275,6 +294,7 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         if (st == DMRG_OK) st = materialize(C, mr, Rb, H->TR, H->TMR, stream);
         if (st != DMRG_OK) return st;
     }
+    clk.mark("materialize");
     auto L = [&](char k, int p, int q) -> const TransOp* {
         auto it = Lx.find(okey(k, p, q));
         return it == Lx.end() ? nullptr : &it->second;
@@ -318,6 +338,7 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         else if (t.kind == '1') H->n1++;
         else H->nh++;
     }
+    clk.mark("terms");
     // wavefunction layout
     const Basis& lb = Lb.basis;
     const Basis& rb = Rb.basis;
@@ -342,165 +363,242 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
     struct TI { std::vector<const Comp*> x[4], y[4]; int piY; };
     std::vector<TI> ti(terms.size());
     for (size_t t = 0; t < terms.size(); ++t) {
+        for (int sb = 0; sb < 4; ++sb) {
+            int n = 0;
+            for (const Comp& c : terms[t].Y.comps) n += (c.sb == sb);
+            if (n > 64) return fail(DMRG_E_STATE, "more than 64 right components on one transition");
+        }
         for (const Comp& c : terms[t].X.comps) ti[t].x[c.sb].push_back(&c);
         for (const Comp& c : terms[t].Y.comps) ti[t].y[c.sb].push_back(&c);
         ti[t].piY = terms[t].Y.par;
     }
+    const size_t NT = terms.size();
+    // validity of an output block (a', s1', s2', b')
+    auto out_block = [&](int a2, int s1, int s2, int b2) -> int {
+        if (a2 < 0) return -1;
+        const int bi = H->blk_index[(a2 * 4 + s1) * 4 + s2];
+        return (bi >= 0 && H->blocks[bi].b == b2) ? bi : -1;
+    };
+    // X comp maps source sector a -> bra (or -1)
+    auto xmap = [&](const Comp* xc, int a, int64_t& off, int& ld, bool& tr) -> int {
+        if (xc->ref.type == 0) { off = -1; ld = 0; tr = false; return a; }
+        int bra;
+        if (!xc->ref.block(a, bra, off, ld, tr)) return -1;
+        return bra;
+    };
+    auto ymap = xmap;
+    struct Local {
+        WorkList wl;
+        std::vector<dmrgk::DiagBlock> dbl;
+        std::vector<dmrgk::DiagTerm> dtm;
+        std::unordered_map<int64_t, int64_t> ops;
+        std::vector<double> lfx, lfy, rfx, rfy;
+    };
+    auto work = [&](size_t o0, size_t o1, Local& Lc) {
+        Lc.lfx.assign(NT, 0.0); Lc.lfy.assign(NT, 0.0); Lc.rfx.assign(NT, 0.0); Lc.rfy.assign(NT, 0.0);
+        WorkList& wl = Lc.wl;
+        auto note = [&](int buf, int64_t o, int64_t n) { Lc.ops[((int64_t)buf << 56) ^ o] = n; };
+        for (size_t o = o0; o < o1; ++o) {
+            const PsiBlock& O = H->blocks[o];
+            const int g0 = (int)wl.groups.size();
+            int maxmu = 0;
+            dmrgk::DiagBlock db{};
+            db.off = O.off;
+            db.ma = O.ma;
+            db.mb = O.mb;
+            db.c0 = (int)Lc.dtm.size();
+            for (size_t t = 0; t < NT; ++t) {
+                const auto& xs = ti[t].x[O.s1];
+                const auto& ys = ti[t].y[O.s2];
+                if (xs.empty() || ys.empty()) continue;
+                if (ys.size() > 64) continue;   // guarded below at term construction
+                const Term& T = terms[t];
+                struct Src { const Comp* x = nullptr; double xid = 0.0, xco = 0.0; int a = -1, ld = 0; int64_t off = 0; bool tr = false; };
+                Src src[4];
+                for (const Comp* xc : xs) {
+                    int a;
+                    if (xc->ref.type == 0) a = O.a;
+                    else {
+                        a = lb.find(lb.q[O.a] - xc->ref.dq());
+                        if (a < 0) continue;
+                    }
+                    int64_t off; int ld; bool tr;
+                    if (xmap(xc, a, off, ld, tr) != O.a) continue;
+                    const int s1 = xc->sk;
+                    Src& S = src[s1];
+                    S.a = a;
+                    double xco = T.coef * xc->coef;
+                    if (xc->sgn_par && (lb.q[a].n() & 1)) xco = -xco;
+                    if (ti[t].piY && ((lb.q[a].n() + kSiteQ[s1].n()) & 1)) xco = -xco;
+                    if (xc->ref.type == 0) S.xid += xco;
+                    else { S.x = xc; S.xco = xco; S.off = off; S.ld = ld; S.tr = tr; }
+                }
+                uint64_t yused = 0;
+                for (int s1 = 0; s1 < 4; ++s1) {
+                    const Src& S = src[s1];
+                    if (S.a < 0 || (!S.x && S.xid == 0.0)) continue;
+                    const int a = S.a;
+                    dmrgk::Group g{};
+                    g.mu = lb.m[a];
+                    g.c0 = (int)wl.contribs.size();
+                    g.xid_coef = S.xid;
+                    int xb = -1;
+                    if (S.x) {
+                        xb = buf_of(H, S.x->ref.set);
+                        g.x_off = S.off;
+                        g.ldx = S.ld;
+                        g.x_coef = S.xco;
+                        g.flags = xb | dmrgk::G_HAS_X | (S.tr ? dmrgk::G_TRANS_X : 0);
+                    }
+                    for (size_t yi = 0; yi < ys.size(); ++yi) {
+                        const Comp* yc = ys[yi];
+                        int b;
+                        if (yc->ref.type == 0) b = O.b;
+                        else {
+                            b = rb.find(rb.q[O.b] - yc->ref.dq());
+                            if (b < 0) continue;
+                        }
+                        int64_t yoff; int ldy; bool ytr;
+                        if (ymap(yc, b, yoff, ldy, ytr) != O.b) continue;
+                        const int s2 = yc->sk;
+                        const int bi = out_block(a, s1, s2, b);
+                        if (bi < 0) continue;
+                        const PsiBlock& I = H->blocks[bi];
+                        dmrgk::Contrib c{};
+                        c.a_off = I.off;
+                        c.lda = I.mb;
+                        c.k = I.mb;
+                        c.alpha = yc->coef;
+                        c.flags = 2;
+                        if (yc->ref.type == 0) {
+                            c.flags |= dmrgk::F_ID_B;
+                        } else {
+                            const int yb = buf_of(H, yc->ref.set);
+                            c.b_off = yoff;
+                            c.ldb = ldy;
+                            c.flags |= (yb << 3) | (ytr ? 0 : dmrgk::F_TRANS_B);
+                            note(yb, yoff, (int64_t)O.mb * I.mb);
+                            yused |= 1ull << yi;
+                            // right-first: psi_I . Y^T once per (y, I); the U block it feeds
+                            // is counted at its first consumer (left component order)
+                            bool first = false;
+                            for (const Comp& xq : T.X.comps) {
+                                if (xq.sk != s1) continue;
+                                int64_t o_; int l_; bool t_;
+                                const int aa = xmap(&xq, a, o_, l_, t_);
+                                if (aa < 0 || out_block(aa, xq.sb, O.s2, O.b) < 0) continue;
+                                first = (aa == O.a && xq.sb == O.s1);
+                                break;
+                            }
+                            if (first) Lc.rfy[t] += 2.0 * I.ma * I.mb * O.mb;
+                        }
+                        wl.contribs.push_back(c);
+                        if (S.x) {
+                            // left-first: X . psi_I once per (x, I), counted at the first right
+                            // component (term order) that consumes T(a', s1', s2, b)
+                            bool first = false;
+                            for (const Comp& yq : T.Y.comps) {
+                                if (yq.sk != s2) continue;
+                                int64_t o_; int l_; bool t_;
+                                const int bb = ymap(&yq, b, o_, l_, t_);
+                                if (bb < 0 || out_block(O.a, O.s1, yq.sb, bb) < 0) continue;
+                                first = (&yq == yc);
+                                break;
+                            }
+                            if (first) Lc.lfx[t] += 2.0 * O.ma * I.ma * I.mb;
+                        }
+                        if (I.a == O.a && s1 == O.s1 && s2 == O.s2 && I.b == O.b) {
+                            dmrgk::DiagTerm d{};
+                            d.y_off = -1;
+                            if (yc->ref.type != 0) {
+                                d.y_off = yoff;
+                                d.ldy = ldy;
+                                d.ybuf = buf_of(H, yc->ref.set);
+                            }
+                            if (S.x) {
+                                d.coef = S.xco * yc->coef;
+                                d.x_off = S.off;
+                                d.ldx = S.ld;
+                                d.xbuf = xb;
+                                Lc.dtm.push_back(d);
+                            }
+                            if (S.xid != 0.0) {
+                                d.coef = S.xid * yc->coef;
+                                d.x_off = -1;
+                                Lc.dtm.push_back(d);
+                            }
+                        }
+                    }
+                    g.c1 = (int)wl.contribs.size();
+                    if (g.c1 == g.c0) continue;
+                    wl.groups.push_back(g);
+                    maxmu = std::max(maxmu, g.mu);
+                    if (S.x) {
+                        Lc.rfx[t] += 2.0 * O.ma * lb.m[a] * O.mb;
+                        note(xb, S.off, (int64_t)O.ma * lb.m[a]);
+                    }
+                }
+                // left-first: T . Y^T once per (output, y)
+                for (size_t yi = 0; yi < ys.size(); ++yi)
+                    if (yused >> yi & 1) {
+                        const Comp* yc = ys[yi];
+                        const int b = rb.find(rb.q[O.b] - yc->ref.dq());
+                        Lc.lfy[t] += 2.0 * O.ma * rb.m[b] * O.mb;
+                    }
+            }
+            db.c1 = (int)Lc.dtm.size();
+            Lc.dbl.push_back(db);
+            emit_block_tasks(wl, 3, O.off, O.mb, O.ma, O.mb, g0, (int)wl.groups.size(), maxmu);
+        }
+    };
+    const size_t nblk = H->blocks.size();
+    unsigned nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (nblk < 64) nth = 1;
+    std::vector<Local> loc(nth);
+    {
+        // interleaved chunks balance the uneven cost of output blocks
+        std::vector<std::vector<std::pair<size_t, size_t>>> chunks(nth);
+        const size_t cs = 8;
+        size_t k = 0;
+        for (size_t o = 0; o < nblk; o += cs, ++k) chunks[k % nth].push_back({o, std::min(nblk, o + cs)});
+        std::vector<std::vector<Local>> parts(nth);
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < nth; ++t)
+            th.emplace_back([&, t]() {
+                for (auto& r : chunks[t]) {
+                    parts[t].emplace_back();
+                    work(r.first, r.second, parts[t].back());
+                }
+            });
+        for (auto& x : th) x.join();
+        // reassemble in output-block order (chunk k went to thread k % nth)
+        std::vector<Local> ordered;
+        std::vector<size_t> pos(nth, 0);
+        for (size_t kk = 0; kk < k; ++kk) ordered.push_back(std::move(parts[kk % nth][pos[kk % nth]++]));
+        loc.swap(ordered);
+    }
     WorkList wl;
-    std::vector<double> lfx(terms.size(), 0.0), lfy(terms.size(), 0.0), rfx(terms.size(), 0.0),
-        rfy(terms.size(), 0.0);
-    std::vector<std::unordered_set<uint64_t>> lx_seen(terms.size()), ry_seen(terms.size());
     std::vector<dmrgk::DiagBlock> dbl;
     std::vector<dmrgk::DiagTerm> dtm;
-    std::unordered_set<int64_t> seen_ops;
-    int64_t op_bytes = 0;
-    auto note = [&](int buf, int64_t o, int64_t n) {
-        const int64_t key = ((int64_t)buf << 56) ^ o;
-        if (seen_ops.insert(key).second) op_bytes += n;
-    };
-    struct Src { const Comp* x = nullptr; double xid = 0.0; double xco = 0.0; int a = -1; int bra, ld; int64_t off; bool tr; };
-    for (size_t o = 0; o < H->blocks.size(); ++o) {
-        const PsiBlock& O = H->blocks[o];
-        const int g0 = (int)wl.groups.size();
-        int maxmu = 0;
-        dmrgk::DiagBlock db{};
-        db.off = O.off;
-        db.ma = O.ma;
-        db.mb = O.mb;
-        db.c0 = (int)dtm.size();
-        for (size_t t = 0; t < terms.size(); ++t) {
-            const auto& xs = ti[t].x[O.s1];
-            const auto& ys = ti[t].y[O.s2];
-            if (xs.empty() || ys.empty()) continue;
-            // sources (a, s1) of this output: one X operator and/or identity
-            Src src[4];
-            for (const Comp* xc : xs) {
-                int a, bra = 0, ld = 0;
-                int64_t off = 0;
-                bool tr = false;
-                if (xc->ref.type == 0) {
-                    a = O.a;
-                } else {
-                    a = lb.find(lb.q[O.a] - xc->ref.dq());
-                    if (a < 0 || !xc->ref.block(a, bra, off, ld, tr) || bra != O.a) continue;
-                }
-                const int s1 = xc->sk;
-                Src& S = src[s1];
-                if (S.a >= 0 && S.a != a) return fail(DMRG_E_STATE, "inconsistent left source");
-                S.a = a;
-                const int nas = lb.q[a].n() + kSiteQ[s1].n();
-                double xco = terms[t].coef * xc->coef;
-                if (xc->sgn_par && (lb.q[a].n() & 1)) xco = -xco;
-                if (ti[t].piY && (nas & 1)) xco = -xco;
-                if (xc->ref.type == 0) {
-                    S.xid += xco;
-                } else {
-                    if (S.x) return fail(DMRG_E_STATE, "two left operators on one transition");
-                    S.x = xc;
-                    S.xco = xco;
-                    S.bra = bra;
-                    S.ld = ld;
-                    S.off = off;
-                    S.tr = tr;
-                }
-            }
-            for (int s1 = 0; s1 < 4; ++s1) {
-                const Src& S = src[s1];
-                if (S.a < 0 || (!S.x && S.xid == 0.0)) continue;
-                const int a = S.a;
-                dmrgk::Group g{};
-                g.mu = lb.m[a];
-                g.c0 = (int)wl.contribs.size();
-                g.xid_coef = S.xid;
-                int xb = -1;
-                if (S.x) {
-                    xb = buf_of(H, S.x->ref.set);
-                    g.x_off = S.off;
-                    g.ldx = S.ld;
-                    g.x_coef = S.xco;
-                    g.flags = xb | dmrgk::G_HAS_X | (S.tr ? dmrgk::G_TRANS_X : 0);
-                }
-                double fy = 0.0;
-                for (const Comp* yc : ys) {
-                    int b, bb = 0, ldy = 0;
-                    int64_t yoff = 0;
-                    bool ytr = false;
-                    if (yc->ref.type == 0) {
-                        b = O.b;
-                    } else {
-                        b = rb.find(rb.q[O.b] - yc->ref.dq());
-                        if (b < 0 || !yc->ref.block(b, bb, yoff, ldy, ytr) || bb != O.b) continue;
-                    }
-                    const int s2 = yc->sk;
-                    const int bi = H->blk_index[(a * 4 + s1) * 4 + s2];
-                    if (bi < 0 || H->blocks[bi].b != b) continue;
-                    const PsiBlock& I = H->blocks[bi];
-                    dmrgk::Contrib c{};
-                    c.a_off = I.off;
-                    c.lda = I.mb;
-                    c.k = I.mb;
-                    c.alpha = yc->coef;
-                    c.flags = 2;
-                    const uint64_t yci = (uint64_t)(yc - terms[t].Y.comps.data());
-                    if (yc->ref.type == 0) {
-                        c.flags |= dmrgk::F_ID_B;
-                    } else {
-                        // B[k=b][n=b'] = Y[b'][b]
-                        const int yb = buf_of(H, yc->ref.set);
-                        c.b_off = yoff;
-                        c.ldb = ldy;
-                        c.flags |= (yb << 3) | (ytr ? 0 : dmrgk::F_TRANS_B);
-                        fy += 2.0 * I.ma * I.mb * O.mb;
-                        note(yb, yoff, (int64_t)O.mb * I.mb);
-                        if (ry_seen[t].insert((yci << 32) | (uint64_t)bi).second)
-                            rfy[t] += 2.0 * I.ma * I.mb * O.mb;
-                        lfy[t] += 2.0 * O.ma * I.mb * O.mb;
-                    }
-                    wl.contribs.push_back(c);
-                    if (S.x) {
-                        const uint64_t xci = (uint64_t)(S.x - terms[t].X.comps.data());
-                        if (lx_seen[t].insert((xci << 32) | (uint64_t)bi).second)
-                            lfx[t] += 2.0 * O.ma * I.ma * I.mb;
-                    }
-                    if (I.a == O.a && s1 == O.s1 && s2 == O.s2 && I.b == O.b) {
-                        dmrgk::DiagTerm d{};
-                        d.y_off = -1;
-                        if (yc->ref.type != 0) {
-                            d.y_off = yoff;
-                            d.ldy = ldy;
-                            d.ybuf = buf_of(H, yc->ref.set);
-                        }
-                        if (S.x) {
-                            d.coef = S.xco * yc->coef;
-                            d.x_off = S.off;
-                            d.ldx = S.ld;
-                            d.xbuf = xb;
-                            dtm.push_back(d);
-                        }
-                        if (S.xid != 0.0) {
-                            d.coef = S.xid * yc->coef;
-                            d.x_off = -1;
-                            dtm.push_back(d);
-                        }
-                    }
-                }
-                g.c1 = (int)wl.contribs.size();
-                if (g.c1 == g.c0) continue;
-                wl.groups.push_back(g);
-                maxmu = std::max(maxmu, g.mu);
-                (void)fy;
-                if (S.x) {
-                    rfx[t] += 2.0 * O.ma * lb.m[a] * O.mb;
-                    note(xb, S.off, (int64_t)O.ma * lb.m[a]);
-                }
-            }
-        }
-        db.c1 = (int)dtm.size();
-        dbl.push_back(db);
-        emit_block_tasks(wl, 3, O.off, O.mb, O.ma, O.mb, g0, (int)wl.groups.size(), maxmu);
+    std::unordered_map<int64_t, int64_t> opsz;
+    std::vector<double> lfx(NT, 0.0), lfy(NT, 0.0), rfx(NT, 0.0), rfy(NT, 0.0);
+    for (Local& Lc : loc) {
+        const int goff = (int)wl.groups.size(), coff = (int)wl.contribs.size(), doff = (int)dtm.size();
+        for (int c = 0; c < dmrgk::kNumClass; ++c)
+            for (dmrgk::Task t : Lc.wl.task[c]) { t.g0 += goff; t.g1 += goff; wl.task[c].push_back(t); }
+        for (dmrgk::Group g : Lc.wl.groups) { g.c0 += coff; g.c1 += coff; wl.groups.push_back(g); }
+        wl.contribs.insert(wl.contribs.end(), Lc.wl.contribs.begin(), Lc.wl.contribs.end());
+        for (dmrgk::DiagBlock d : Lc.dbl) { d.c0 += doff; d.c1 += doff; dbl.push_back(d); }
+        dtm.insert(dtm.end(), Lc.dtm.begin(), Lc.dtm.end());
+        for (auto& kv : Lc.ops) opsz[kv.first] = kv.second;
+        for (size_t t = 0; t < NT; ++t) { lfx[t] += Lc.lfx[t]; lfy[t] += Lc.lfy[t]; rfx[t] += Lc.rfx[t]; rfy[t] += Lc.rfy[t]; }
+        Lc = Local();
     }
-    std::vector<double> lf(terms.size()), rf(terms.size());
-    for (size_t t = 0; t < terms.size(); ++t) {
+    int64_t op_bytes = 0;
+    for (auto& kv : opsz) op_bytes += kv.second;
+    clk.mark("work list");
+    std::vector<double> lf(NT), rf(NT);
+    for (size_t t = 0; t < NT; ++t) {
         lf[t] = lfx[t] + lfy[t];
         rf[t] = rfx[t] + rfy[t];
     }
@@ -527,8 +625,13 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
             if (d.y_off >= 0 && (d.ybuf < 0 || d.ybuf >= 8 || d.y_off >= sz[d.ybuf])) return fail(DMRG_E_STATE, "diag Y");
         }
     }
+    clk.mark("validate");
+    if (clk.on)
+        std::fprintf(stderr, "[dmrg] tasks %zu groups %zu contribs %zu diag terms %zu\n", wl.ntasks(),
+                     wl.groups.size(), wl.contribs.size(), dtm.size());
     dmrg_status st = upload_work(C, wl, H->work, stream);
     if (st != DMRG_OK) return st;
+    clk.mark("upload");
     // diagonal lists
     {
         const int64_t bytes = ((int64_t)dbl.size() * sizeof(dmrgk::DiagBlock) + 255) / 256 * 256 +

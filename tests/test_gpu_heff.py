@@ -194,3 +194,52 @@ def test_mixed_vs_fp64_energy():
         es[prec] = e[0]
     _close(H, L, R, ctx)
     assert abs(es[0] - es[1]) <= 1e-8
+
+
+@pytest.mark.parametrize("K,N,M,seed", [(12, 12, None, 81), (14, 14, 1000, 82)])
+def test_large_sector_twins(K, N, M, seed):
+    """Sectors of 100 and 166 rows: the 128- and 320-row kernel classes, FP64 and FP32."""
+    p = synth.make_problem(K, N, 0, M, seed)
+    ref = blockops.MiddleHeff(p, "CN").apply(p.psi)
+    ctx, L, R, H, keep = _step(p, arena=8 << 30)
+    got = _apply(H, p.psi)
+    got32 = _apply(H, p.psi, _lib().DMRG_PREC_F32)
+    _close(H, L, R, ctx)
+    e64, e32 = _rel(got, ref), _rel(got32, ref)
+    print(f"[gpu] twin K={K} M={M} f64={e64:.2e} f32={e32:.2e}", flush=True)
+    assert e64 <= 1e-12
+    assert e32 <= 1e-5
+
+
+def test_c3_full_size_invariants():
+    """K=54, M=2000 at full size: FP32 vs FP64 products, hermiticity, linearity,
+    bitwise-identical repeats (no oracle product at this size: parity is pinned by
+    the twins above and these properties)."""
+    import torch
+    d = _lib()
+    p = synth.config_problem("C3")
+    ctx, L, R, H, keep = _step(p, arena=100 << 30)
+    n = H.dim
+    xs = synth.random_vectors(n, 2, 11)
+    x = torch.from_numpy(xs[0].copy()).cuda()
+    y = torch.from_numpy(xs[1].copy()).cuda()
+    hx, hy, hx2, hxy = (torch.empty_like(x) for _ in range(4))
+    H.apply(x, hx)
+    H.apply(y, hy)
+    H.apply(x, hx2)
+    H.apply(x + 2.0 * y, hxy)
+    x32, h32 = x.float(), torch.empty(n, dtype=torch.float32, device="cuda")
+    H.apply(x32, h32, d.DMRG_PREC_F32)
+    torch.cuda.synchronize()
+    a = float(torch.dot(x, hy))
+    b = float(torch.dot(hx, y))
+    nrm = float(hx.norm())
+    e32 = float((h32.double() - hx).norm() / nrm)
+    lin = float((hxy - hx - 2.0 * hy).norm() / nrm)
+    print(f"[gpu] C3 herm {abs(a - b):.3e} f32 {e32:.3e} lin {lin:.3e}", flush=True)
+    same = bool(torch.equal(hx, hx2))
+    _close(H, L, R, ctx)
+    assert same
+    assert abs(a - b) <= 1e-12 * nrm
+    assert lin <= 1e-13
+    assert e32 <= 1e-5
