@@ -102,6 +102,9 @@ typedef struct {
     int32_t precision;        /* DMRG_PREC_F64, or DMRG_PREC_F32 for the mixed policy */
     double switch_tol;        /* mixed policy: FP32 matvecs while max residual > switch_tol */
     int32_t fixed_iters;      /* > 0: run exactly this many iterations (timing mode) */
+    double precond_clamp;     /* diagonal preconditioner t = r / (theta - d) with |theta - d|
+                                 clamped >= precond_clamp; 0 selects 0.1; < 0 disables the
+                                 preconditioner (t = r) */
 } dmrg_dav_opts;
 
 typedef struct {

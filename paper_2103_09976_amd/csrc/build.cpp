@@ -21,6 +21,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -396,9 +398,6 @@ static dmrg_status renormalize_ops(Ctx* C, const OpSetImpl& old, const OpSetImpl
     nw.lookup.clear();
     for (size_t i = 0; i < G.keys.size(); ++i)
         nw.add_op(G.kinds[i], G.idx[i].first, G.idx[i].second, G.ops[i].dq, G.ops[i].par);
-    for (int m : nw.basis.m)
-        if (m > dmrgk::kClassRows[dmrgk::kNumClass - 1])
-            return fail(DMRG_E_UNSUPPORTED, "sector dimension above 320");
     dmrg_status st = alloc_set(C, nw);
     if (st != DMRG_OK) return st;
     WorkList wl;
@@ -682,6 +681,13 @@ dmrg_status dmrg_build_block(dmrg_ctx* ctx, int32_t side, int32_t n_sites, const
             nw.orbs.insert(nw.orbs.end(), cur.orbs.begin(), cur.orbs.end());
         }
         nw.nsites = j + 1;
+        if (std::getenv("DMRG_VERBOSE")) {
+            size_t nops = 0;
+            for (auto& F : nw.fams) nops += F.keys.size();
+            std::fprintf(stderr, "[dmrg] %s site %d: M=%lld sectors=%d ops=%zu set=%.2f GB arena=%.2f GB peak=%.2f GB\n",
+                         side == DMRG_LEFT ? "left" : "right", j, (long long)nw.basis.total, nw.basis.size(), nops,
+                         nw.elems * 8.0 / 1e9, ctx->arena.used / 1e9, ctx->arena.peak / 1e9);
+        }
         free_set(ctx, cur);
         cur = std::move(nw);
     }

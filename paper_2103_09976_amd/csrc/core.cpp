@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <tuple>
 
 #include "core.hpp"
 
@@ -377,6 +378,8 @@ void WorkList::clear() {
     for (auto& t : task) t.clear();
     groups.clear();
     contribs.clear();
+    reduces.clear();
+    partial_elems = 0;
 }
 
 size_t WorkList::ntasks() const {
@@ -410,9 +413,182 @@ void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int 
     }
 }
 
+// Tiles taller than the largest row class (320) are split exactly: output
+// rows into row tiles, the inner dimension mu of X . U into chunks (a group
+// becomes one group per chunk; its identity part follows the output rows).
+void split_large(WorkList& w) {
+    const int CAP = dmrgk::kClassRows[dmrgk::kNumClass - 1];
+    bool need = false;
+    for (auto& T : w.task)
+        for (const dmrgk::Task& t : T) {
+            if (t.m > CAP) need = true;
+            for (int g = t.g0; g < t.g1 && !need; ++g) need = w.groups[g].mu > CAP;
+            if (need) break;
+        }
+    if (!need) return;
+    std::vector<dmrgk::Task> all;
+    for (auto& T : w.task) {
+        all.insert(all.end(), T.begin(), T.end());
+        T.clear();
+    }
+    auto shift_contrib = [](dmrgk::Contrib c, int u0) {
+        const bool ida = c.flags & dmrgk::F_ID_A, idb = c.flags & dmrgk::F_ID_B;
+        if (ida && idb) c.a_off += u0;                       // diagonal offset of an identity
+        else if (ida) c.b_off += (c.flags & dmrgk::F_TRANS_B) ? u0 : (int64_t)u0 * c.ldb;
+        else c.a_off += (c.flags & dmrgk::F_TRANS_A) ? u0 : (int64_t)u0 * c.lda;
+        return c;
+    };
+    std::map<std::tuple<int, int, int>, std::pair<int, int>> done;   // (g0, g1, r0) -> new range
+    std::vector<dmrgk::Group> ng = w.groups;
+    std::vector<dmrgk::Contrib> nc = w.contribs;
+    for (const dmrgk::Task& t : all) {
+        bool big = t.m > CAP;
+        for (int g = t.g0; g < t.g1 && !big; ++g) big = w.groups[g].mu > CAP;
+        if (!big) {
+            int mx = t.m;
+            for (int g = t.g0; g < t.g1; ++g) mx = std::max(mx, w.groups[g].mu);
+            w.task[row_class(mx)].push_back(t);
+            continue;
+        }
+        for (int r0 = 0; r0 < t.m; r0 += CAP) {
+            const int rm = std::min(CAP, t.m - r0);
+            auto key = std::make_tuple(t.g0, t.g1, r0);
+            auto it = done.find(key);
+            if (it == done.end()) {
+                const int g0 = (int)ng.size();
+                for (int g = t.g0; g < t.g1; ++g) {
+                    const dmrgk::Group& G = w.groups[g];
+                    if (G.flags & dmrgk::G_HAS_X) {
+                        for (int u0 = 0; u0 < G.mu; u0 += CAP) {
+                            dmrgk::Group H = G;
+                            H.mu = std::min(CAP, G.mu - u0);
+                            H.xid_coef = 0.0;
+                            H.x_off += (G.flags & dmrgk::G_TRANS_X) ? (int64_t)u0 * G.ldx + r0
+                                                                    : (int64_t)r0 * G.ldx + u0;
+                            H.c0 = (int)nc.size();
+                            for (int c = G.c0; c < G.c1; ++c) nc.push_back(shift_contrib(w.contribs[c], u0));
+                            H.c1 = (int)nc.size();
+                            ng.push_back(H);
+                        }
+                    }
+                    if (G.xid_coef != 0.0) {
+                        dmrgk::Group H = G;
+                        H.flags &= ~(dmrgk::G_HAS_X | dmrgk::G_TRANS_X);
+                        H.x_coef = 0.0;
+                        H.mu = rm;
+                        H.c0 = (int)nc.size();
+                        for (int c = G.c0; c < G.c1; ++c) nc.push_back(shift_contrib(w.contribs[c], r0));
+                        H.c1 = (int)nc.size();
+                        ng.push_back(H);
+                    }
+                }
+                it = done.emplace(key, std::make_pair(g0, (int)ng.size())).first;
+            }
+            dmrgk::Task u = t;
+            u.c_off += (int64_t)r0 * t.ldc;
+            u.m = rm;
+            u.g0 = it->second.first;
+            u.g1 = it->second.second;
+            int mx = rm;
+            for (int g = u.g0; g < u.g1; ++g) mx = std::max(mx, ng[g].mu);
+            w.task[row_class(mx)].push_back(u);
+        }
+    }
+    w.groups.swap(ng);
+    w.contribs.swap(nc);
+}
+
+// Cost model of one group for a tile of m rows: MFMA work of the A.B
+// products and of X.U, plus a fixed per-group and per-contribution overhead
+// (fragment loads, the LDS round trip of U, barriers) in flop equivalents.
+static double group_cost(const WorkList& w, const dmrgk::Group& G, int m) {
+    double f = 16384.0;
+    if (G.flags & dmrgk::G_HAS_X) f += 2.0 * m * G.mu * dmrgk::kTN;
+    for (int c = G.c0; c < G.c1; ++c) {
+        const dmrgk::Contrib& q = w.contribs[c];
+        f += 4096.0;
+        if (!(q.flags & (dmrgk::F_ID_A | dmrgk::F_ID_B))) f += 2.0 * G.mu * q.k * dmrgk::kTN;
+    }
+    return f;
+}
+
+double task_cost(const WorkList& w, const dmrgk::Task& t) {
+    double f = 0;
+    for (int g = t.g0; g < t.g1; ++g) f += group_cost(w, w.groups[g], t.m);
+    return f;
+}
+
+void balance_work(WorkList& w, int target_tasks) {
+    double total = 0;
+    for (auto& T : w.task)
+        for (const dmrgk::Task& t : T) total += task_cost(w, t);
+    if (total <= 0 || target_tasks < 1) return;
+    const double cap = total / target_tasks;
+    std::vector<std::pair<double, dmrgk::Task>> out[dmrgk::kNumClass];
+    int64_t poff = w.partial_elems;
+    std::vector<double> gc;
+    for (auto& T : w.task) {
+        for (const dmrgk::Task& t : T) {
+            gc.resize(t.g1 - t.g0);
+            double tc = 0;
+            for (int g = t.g0; g < t.g1; ++g) tc += gc[g - t.g0] = group_cost(w, w.groups[g], t.m);
+            const int nchunk = (int)std::min<double>(std::ceil(tc / cap), t.g1 - t.g0);
+            if (nchunk <= 1) {
+                int mx = t.m;
+                for (int g = t.g0; g < t.g1; ++g) mx = std::max(mx, w.groups[g].mu);
+                out[row_class(mx)].emplace_back(tc, t);
+                continue;
+            }
+            // greedy cut at multiples of tc / nchunk
+            const double per = tc / nchunk;
+            int slot = 0;
+            int a = t.g0;
+            double run = 0, done = 0;
+            const int64_t slot_elems = (int64_t)t.m * dmrgk::kTN;
+            for (int g = t.g0; g < t.g1; ++g) {
+                run += gc[g - t.g0];
+                const bool last = g + 1 == t.g1;
+                if (!last && done + run < per * (slot + 1)) continue;
+                dmrgk::Task u = t;
+                u.g0 = a;
+                u.g1 = g + 1;
+                u.c_off = poff + slot * slot_elems;
+                u.ldc = dmrgk::kTN;
+                u.cbuf = dmrgk::kPartialBuf | (1 << 9);
+                int mx = t.m;
+                for (int h = u.g0; h < u.g1; ++h) mx = std::max(mx, w.groups[h].mu);
+                out[row_class(mx)].emplace_back(run, u);
+                done += run;
+                run = 0;
+                a = g + 1;
+                ++slot;
+            }
+            dmrgk::Reduce r;
+            r.c_off = t.c_off;
+            r.poff = poff;
+            r.ldc = t.ldc;
+            r.m = t.m;
+            r.n = t.n;
+            r.col0 = t.col0;
+            r.nslot = slot;
+            r.cbuf = t.cbuf & (15 | 256);
+            w.reduces.push_back(r);
+            poff += slot * slot_elems;
+        }
+    }
+    w.partial_elems = poff;
+    for (int c = 0; c < dmrgk::kNumClass; ++c) {
+        std::stable_sort(out[c].begin(), out[c].end(),
+                         [](const auto& x, const auto& y) { return x.first > y.first; });
+        w.task[c].clear();
+        for (auto& e : out[c]) w.task[c].push_back(e.second);
+    }
+}
+
 // Every element a task can touch must lie inside its buffer: checked on the
 // host before any work list reaches the device.
-dmrg_status validate_work(const WorkList& w, const int64_t* size) {
+dmrg_status validate_work(WorkList& w, const int64_t* size) {
+    split_large(w);
     auto in = [&](int buf, int64_t first, int64_t last) {
         return buf >= 0 && buf < dmrgk::kMaxBuf && first >= 0 && last < size[buf] && first <= last;
     };
@@ -420,9 +596,12 @@ dmrg_status validate_work(const WorkList& w, const int64_t* size) {
         const int cap = dmrgk::kClassRows[cls];
         int lg0 = -1, lg1 = -1;
         for (const dmrgk::Task& t : w.task[cls]) {
-            if (t.m > cap || t.m < 1 || t.n < 1 || t.col0 < 0 || t.col0 >= t.n || t.ldc < t.n)
+            const bool local = (t.cbuf >> 9) & 1;
+            if (t.m > cap || t.m < 1 || t.n < 1 || t.col0 < 0 || t.col0 >= t.n ||
+                (local ? t.ldc != dmrgk::kTN : t.ldc < t.n))
                 return fail(DMRG_E_STATE, "work list: bad task shape");
-            if (!in(t.cbuf & 7, t.c_off, t.c_off + (int64_t)(t.m - 1) * t.ldc + t.n - 1))
+            if (local ? !in(t.cbuf & 15, t.c_off, t.c_off + (int64_t)t.m * dmrgk::kTN - 1)
+                      : !in(t.cbuf & 15, t.c_off, t.c_off + (int64_t)(t.m - 1) * t.ldc + t.n - 1))
                 return fail(DMRG_E_STATE, "work list: output out of bounds");
             if (t.g0 == lg0 && t.g1 == lg1) continue;
             lg0 = t.g0;
@@ -448,7 +627,10 @@ dmrg_status validate_work(const WorkList& w, const int64_t* size) {
                     const bool ida = q.flags & dmrgk::F_ID_A, idb = q.flags & dmrgk::F_ID_B;
                     const bool ta = q.flags & dmrgk::F_TRANS_A, tb = q.flags & dmrgk::F_TRANS_B;
                     const int abuf = q.flags & 7, bbuf = (q.flags >> 3) & 7;
-                    if (ida && idb) continue;
+                    if (ida && idb) {
+                        if (q.a_off < 0 || q.a_off > 1 << 20) return fail(DMRG_E_STATE, "work list: identity offset");
+                        continue;
+                    }
                     if (ida) {          // U += alpha B[0:mu, 0:n]
                         const int64_t last = tb ? q.b_off + (int64_t)(t.n - 1) * q.ldb + G.mu - 1
                                                 : q.b_off + (int64_t)(G.mu - 1) * q.ldb + t.n - 1;
@@ -472,6 +654,14 @@ dmrg_status validate_work(const WorkList& w, const int64_t* size) {
             }
         }
     }
+    for (const dmrgk::Reduce& r : w.reduces) {
+        if (r.m < 1 || r.n < 1 || r.col0 < 0 || r.col0 >= r.n || r.ldc < r.n || r.nslot < 1)
+            return fail(DMRG_E_STATE, "work list: bad reduction shape");
+        if (!in(r.cbuf & 15, r.c_off, r.c_off + (int64_t)(r.m - 1) * r.ldc + r.n - 1))
+            return fail(DMRG_E_STATE, "work list: reduction output out of bounds");
+        if (!in(dmrgk::kPartialBuf, r.poff, r.poff + (int64_t)r.nslot * r.m * dmrgk::kTN - 1))
+            return fail(DMRG_E_STATE, "work list: partial tiles out of bounds");
+    }
     return DMRG_OK;
 }
 
@@ -486,6 +676,8 @@ dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
     bytes += ((int64_t)w.groups.size() * sizeof(dmrgk::Group) + 255) & ~int64_t(255);
     const int64_t coff = bytes;
     bytes += ((int64_t)w.contribs.size() * sizeof(dmrgk::Contrib) + 255) & ~int64_t(255);
+    const int64_t roff = bytes;
+    bytes += ((int64_t)w.reduces.size() * sizeof(dmrgk::Reduce) + 255) & ~int64_t(255);
     const int64_t reg = ctx->arena.alloc(bytes);
     if (reg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for a work list of " + std::to_string(bytes) + " bytes");
     d.region = reg;
@@ -506,6 +698,11 @@ dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
     if (!w.contribs.empty())
         DMRG_HIP(hipMemcpyAsync(d.contribs, w.contribs.data(), w.contribs.size() * sizeof(dmrgk::Contrib),
                                 hipMemcpyHostToDevice, s));
+    d.reduces = (dmrgk::Reduce*)(base + roff);
+    d.nred = (int)w.reduces.size();
+    if (!w.reduces.empty())
+        DMRG_HIP(hipMemcpyAsync(d.reduces, w.reduces.data(), w.reduces.size() * sizeof(dmrgk::Reduce),
+                                hipMemcpyHostToDevice, s));
     DMRG_HIP(hipStreamSynchronize(s));   // host vectors may be released after return
     return DMRG_OK;
 }
@@ -517,13 +714,17 @@ void free_work(Ctx* ctx, DevWork& d) {
 
 dmrg_status run_work_f64(const DevWork& d, const dmrgk::Bases<double>& b, int nvec, void* stream) {
     for (int c = dmrgk::kNumClass - 1; c >= 0; --c)
-        DMRG_HIP(dmrgk::launch_chain_f64(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec, stream));
+        DMRG_HIP(dmrgk::launch_chain_f64(c, d.variant[c], d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec,
+                                         stream));
+    DMRG_HIP(dmrgk::launch_reduce_f64(d.reduces, d.nred, b, nvec, stream));
     return DMRG_OK;
 }
 
 dmrg_status run_work_f32(const DevWork& d, const dmrgk::Bases<float>& b, int nvec, void* stream) {
     for (int c = dmrgk::kNumClass - 1; c >= 0; --c)
-        DMRG_HIP(dmrgk::launch_chain_f32(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec, stream));
+        DMRG_HIP(dmrgk::launch_chain_f32(c, d.variant[c], d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec,
+                                         stream));
+    DMRG_HIP(dmrgk::launch_reduce_f32(d.reduces, d.nred, b, nvec, stream));
     return DMRG_OK;
 }
 

@@ -213,6 +213,8 @@ struct WorkList {
     std::vector<dmrgk::Task> task[dmrgk::kNumClass];
     std::vector<dmrgk::Group> groups;
     std::vector<dmrgk::Contrib> contribs;
+    std::vector<dmrgk::Reduce> reduces;   // sums of split tasks' partial tiles
+    int64_t partial_elems = 0;            // per-vector size of the partial buffer
     void clear();
     size_t ntasks() const;
 };
@@ -224,10 +226,20 @@ struct DevWork {
     int ntask[dmrgk::kNumClass] = {0, 0, 0};
     dmrgk::Group* groups = nullptr;
     dmrgk::Contrib* contribs = nullptr;
+    dmrgk::Reduce* reduces = nullptr;
+    int nred = 0;
+    int variant[dmrgk::kNumClass] = {0, 0, 0};   // kernel variant per row class
 };
 dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
-// host-side bounds check of every operand of every task; size[b] = elements of buffer b
-dmrg_status validate_work(const WorkList& w, const int64_t* size);
+// splits tiles above 320 rows, then checks every operand of every task on the
+// host; size[b] = elements of buffer b
+dmrg_status validate_work(WorkList& w, const int64_t* size);
+void split_large(WorkList& w);
+// Splits the group ranges of expensive tasks into chunks of about
+// 1/target_tasks of the total cost each (chunks write partial tiles that a
+// reduction sums in fixed order), then orders every class by decreasing cost.
+void balance_work(WorkList& w, int target_tasks);
+double task_cost(const WorkList& w, const dmrgk::Task& t);
 void free_work(Ctx* ctx, DevWork& d);
 int row_class(int rows);
 dmrg_status run_work_f64(const DevWork& d, const dmrgk::Bases<double>& b, int nvec, void* stream);

@@ -30,7 +30,7 @@ namespace {
 struct DavWs {
     Ctx* C;
     int64_t region = -1;
-    double *V, *W, *X, *HX, *R, *diag, *small, *scratch;
+    double *V, *W, *X, *HX, *R, *diag, *small, *scratch, *V2, *W2;
     float *f_in, *f_out;
     int* flag;
 };
@@ -127,8 +127,9 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff* H, int32_t k, double* psi_io, do
     DavWs ws;
     ws.C = C;
     const int64_t nchunk = (dim + 4095) / 4096;
-    const int64_t bytes = ((int64_t)(2 * msub + 3 * k) * dim + dim) * 8 + 2 * (int64_t)k * dim * 4 +
-                          (int64_t)(64 * 64 * 2) * 8 + nchunk * 64 * 64 * 8 + 4096;
+    const int keep = std::min(msub - k, std::max(2 * k, msub / 3));   // Ritz vectors kept at restart
+    const int64_t bytes = ((int64_t)(2 * msub + 3 * k + 2 * keep) * dim + dim) * 8 + 2 * (int64_t)k * dim * 4 +
+                          (int64_t)(64 * 64 * 2) * 8 + nchunk * 64 * 64 * 8 + 16384;
     ws.region = C->arena.alloc(bytes);
     if (ws.region < 0) return fail(DMRG_E_WORKSPACE, "arena too small for the Davidson workspace");
     char* p = C->arena.base + ws.region;
@@ -139,6 +140,8 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff* H, int32_t k, double* psi_io, do
     ws.HX = (double*)take((int64_t)k * dim * 8);
     ws.R = (double*)take((int64_t)k * dim * 8);
     ws.diag = (double*)take(dim * 8);
+    ws.V2 = (double*)take((int64_t)keep * dim * 8);
+    ws.W2 = (double*)take((int64_t)keep * dim * 8);
     ws.small = (double*)take(64 * 64 * 2 * 8);
     ws.scratch = (double*)take(nchunk * 64 * 64 * 8);
     ws.f_in = (float*)take((int64_t)k * dim * 4);
@@ -167,6 +170,7 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff* H, int32_t k, double* psi_io, do
         ++nv;
     }
     int prec = opts->precision;
+    const double clamp = opts->precond_clamp == 0.0 ? 0.1 : opts->precond_clamp;
     st = matvec(H, ws, prec, ws.V, ws.W, nv, dim, stream, &ms_mv, &mv32);
     if (st != DMRG_OK) return st;
     nmv += nv;
@@ -243,6 +247,33 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff* H, int32_t k, double* psi_io, do
             restart = true;
             switched = true;
         }
+        if (restart && !switched && nv > keep) {
+            // thick restart: V <- V Z[:, :keep], W <- W Z[:, :keep], G <- V^T W
+            std::vector<double> Zr((size_t)nv * keep);
+            for (int i = 0; i < nv; ++i)
+                for (int j = 0; j < keep; ++j) Zr[(size_t)i * keep + j] = Z[(size_t)i * nv + j];
+            for (int j0 = 0; j0 < keep; j0 += 32) {
+                const int nj = std::min(32, keep - j0);
+                std::vector<double> Cj((size_t)nv * nj);
+                for (int i = 0; i < nv; ++i)
+                    for (int j = 0; j < nj; ++j) Cj[(size_t)i * nj + j] = Zr[(size_t)i * keep + j0 + j];
+                if ((st = combine(ws, ws.V, nv, Cj, ws.V2 + (int64_t)j0 * dim, nj, dim, 0.0, stream)) != DMRG_OK)
+                    return st;
+                if ((st = combine(ws, ws.W, nv, Cj, ws.W2 + (int64_t)j0 * dim, nj, dim, 0.0, stream)) != DMRG_OK)
+                    return st;
+            }
+            DMRG_HIP(hipMemcpyAsync(ws.V, ws.V2, (int64_t)keep * dim * 8, hipMemcpyDeviceToDevice, s));
+            DMRG_HIP(hipMemcpyAsync(ws.W, ws.W2, (int64_t)keep * dim * 8, hipMemcpyDeviceToDevice, s));
+            nv = keep;
+            std::vector<double> g;
+            if ((st = gram_host(ws, ws.V, nv, ws.W, nv, dim, g, stream)) != DMRG_OK) return st;
+            std::fill(G.begin(), G.end(), 0.0);
+            for (int i = 0; i < nv; ++i)
+                for (int j = 0; j < nv; ++j)
+                    G[(size_t)i * msub + j] = 0.5 * (g[(size_t)i * nv + j] + g[(size_t)j * nv + i]);
+            ++it;
+            continue;
+        }
         if (restart) {
             DMRG_HIP(hipMemcpyAsync(ws.V, ws.X, (int64_t)k * dim * 8, hipMemcpyDeviceToDevice, s));
             nv = k;
@@ -267,7 +298,7 @@ extern "C" dmrg_status dmrg_davidson(dmrg_heff* H, int32_t k, double* psi_io, do
         for (int j = 0; j < k; ++j) {
             if (res[j] <= opts->tol && !fixed) continue;
             double* t = ws.V + (int64_t)nv * dim;
-            DMRG_HIP(dmrgk::launch_precond(ws.R + (int64_t)j * dim, ws.diag, theta[j], t, dim, stream));
+            DMRG_HIP(dmrgk::launch_precond(ws.R + (int64_t)j * dim, ws.diag, theta[j], clamp, t, dim, stream));
             double n0;
             std::vector<double> c;
             if ((st = gram_host(ws, t, 1, t, 1, dim, c, stream)) != DMRG_OK) return st;

@@ -38,9 +38,13 @@ struct PhaseClock {
     }
 };
 
-namespace dmrg {
-
-}  // namespace dmrg
+// Number of equal-cost chunks the H_eff work is cut into (tasks above
+// total/target are split): enough for many workgroups per compute unit so
+// the last wave of the launch is short.  DMRG_BALANCE overrides it.
+static int balance_target() {
+    const char* e = std::getenv("DMRG_BALANCE");
+    return e ? std::atoi(e) : 8192;
+}
 
 using namespace dmrg;
 
@@ -75,6 +79,10 @@ struct dmrg_heff {
     // fp32 mirrors of buffers 0,1,4..7
     int64_t f32_region = -1;
     float* f32[8] = {nullptr};
+    // partial tiles of split tasks (buffer 8), n_roots vectors
+    int64_t part_region = -1;
+    void* part = nullptr;
+    int64_t part_elems = 0;
     int64_t flops = 0;
     int64_t op_bytes64 = 0;
     int n2 = 0, n1 = 0, nh = 0;
@@ -355,10 +363,6 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
                 off += (int64_t)lb.m[a] * rb.m[b];
             }
     H->dim = off;
-    for (int m : lb.m)
-        if (m > 320) return fail(DMRG_E_UNSUPPORTED, "left sector above 320");
-    for (int m : rb.m)
-        if (m > 320) return fail(DMRG_E_UNSUPPORTED, "right sector above 320");
     // per term: components by bra site state
     struct TI { std::vector<const Comp*> x[4], y[4]; int piY; };
     std::vector<TI> ti(terms.size());
@@ -618,6 +622,9 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         sz[5] = H->TR.elems;
         sz[6] = H->TML.elems;
         sz[7] = H->TMR.elems;
+        split_large(wl);
+        balance_work(wl, balance_target());
+        sz[dmrgk::kPartialBuf] = wl.partial_elems;
         dmrg_status vs = validate_work(wl, sz);
         if (vs != DMRG_OK) return vs;
         for (const auto& d : dtm) {
@@ -626,11 +633,37 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         }
     }
     clk.mark("validate");
+    if (clk.on) {
+        // work per task (flops of its groups) -> load-balance picture
+        for (int c = 0; c < dmrgk::kNumClass; ++c) {
+            double tot = 0, mx = 0;
+            std::vector<double> w;
+            for (const dmrgk::Task& t : wl.task[c]) {
+                const double f = task_cost(wl, t);
+                tot += f;
+                mx = std::max(mx, f);
+                w.push_back(f);
+            }
+            std::sort(w.begin(), w.end());
+            if (!w.empty())
+                std::fprintf(stderr, "[dmrg] class %d: tasks %zu work %.3f TF max %.3f GF median %.3f GF p99 %.3f GF\n", c,
+                             w.size(), tot / 1e12, mx / 1e9, w[w.size() / 2] / 1e9, w[w.size() * 99 / 100] / 1e9);
+        }
+    }
     if (clk.on)
-        std::fprintf(stderr, "[dmrg] tasks %zu groups %zu contribs %zu diag terms %zu\n", wl.ntasks(),
-                     wl.groups.size(), wl.contribs.size(), dtm.size());
+        std::fprintf(stderr, "[dmrg] tasks %zu groups %zu contribs %zu reductions %zu partial %.1f MB diag terms %zu\n",
+                     wl.ntasks(), wl.groups.size(), wl.contribs.size(), wl.reduces.size(),
+                     wl.partial_elems * 8.0 * H->n_roots / 1e6, dtm.size());
+    H->part_elems = wl.partial_elems;
+    if (H->part_elems > 0) {
+        H->part_region = C->arena.alloc(H->part_elems * 8 * H->n_roots);
+        if (H->part_region < 0) return fail(DMRG_E_WORKSPACE, "arena too small for partial tiles");
+        H->part = C->arena.base + H->part_region;
+    }
     dmrg_status st = upload_work(C, wl, H->work, stream);
     if (st != DMRG_OK) return st;
+    if (const char* v = std::getenv("DMRG_VARIANT"))   // per-class kernel variant, e.g. "110"
+        for (int c = 0; c < dmrgk::kNumClass && v[c]; ++c) H->work.variant[c] = (v[c] == '1' && c < 2) ? 1 : 0;
     clk.mark("upload");
     // diagonal lists
     {
@@ -651,13 +684,15 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
 
 static dmrgk::Bases<double> bases64(const dmrg_heff* H) {
     dmrgk::Bases<double> b{};
+    b.p[dmrgk::kPartialBuf] = (double*)H->part;
+    b.vstride[dmrgk::kPartialBuf] = H->part_elems;
     b.p[0] = H->Lb->dev;
     b.p[1] = H->Rb->dev;
     b.p[4] = H->TL.dev;
     b.p[5] = H->TR.dev;
     b.p[6] = H->TML.dev;
     b.p[7] = H->TMR.dev;
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < dmrgk::kMaxBuf; ++i)
         if (!b.p[i]) b.p[i] = H->Lb->dev;
     return b;
 }
@@ -732,24 +767,33 @@ dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec, cons
     if (!H || !psi || !sigma) return fail(DMRG_E_ARG, "null argument");
     if (n_vec < 1 || n_vec > 65535) return fail(DMRG_E_ARG, "bad n_vec");
     if (psi == sigma) return fail(DMRG_E_ARG, "psi and sigma must not alias");
-    if (precision == DMRG_PREC_F64) {
-        dmrgk::Bases<double> b = bases64(H);
-        b.p[2] = (double*)psi;
-        b.p[3] = (double*)sigma;
-        b.vstride[2] = b.vstride[3] = H->dim;
-        return run_work_f64(H->work, b, n_vec, stream);
-    }
-    if (precision == DMRG_PREC_F32) {
-        dmrg_status st = ensure_f32(H, stream);
+    if (precision != DMRG_PREC_F64 && precision != DMRG_PREC_F32) return fail(DMRG_E_ARG, "bad precision");
+    // vectors go in batches of at most n_roots: the partial-tile buffer holds that many
+    const int batch = H->part_elems > 0 ? H->n_roots : n_vec;
+    for (int v0 = 0; v0 < n_vec; v0 += batch) {
+        const int nv = std::min(batch, n_vec - v0);
+        dmrg_status st;
+        if (precision == DMRG_PREC_F64) {
+            dmrgk::Bases<double> b = bases64(H);
+            b.p[2] = (double*)psi + (int64_t)v0 * H->dim;
+            b.p[3] = (double*)sigma + (int64_t)v0 * H->dim;
+            b.vstride[2] = b.vstride[3] = H->dim;
+            st = run_work_f64(H->work, b, nv, stream);
+        } else {
+            st = ensure_f32(H, stream);
+            if (st != DMRG_OK) return st;
+            dmrgk::Bases<float> b{};
+            for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
+            b.p[dmrgk::kPartialBuf] = H->part ? (float*)H->part : H->f32[0];
+            b.vstride[dmrgk::kPartialBuf] = H->part_elems;
+            b.p[2] = (float*)psi + (int64_t)v0 * H->dim;
+            b.p[3] = (float*)sigma + (int64_t)v0 * H->dim;
+            b.vstride[2] = b.vstride[3] = H->dim;
+            st = run_work_f32(H->work, b, nv, stream);
+        }
         if (st != DMRG_OK) return st;
-        dmrgk::Bases<float> b{};
-        for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
-        b.p[2] = (float*)psi;
-        b.p[3] = (float*)sigma;
-        b.vstride[2] = b.vstride[3] = H->dim;
-        return run_work_f32(H->work, b, n_vec, stream);
     }
-    return fail(DMRG_E_ARG, "bad precision");
+    return DMRG_OK;
 }
 
 dmrg_status dmrg_heff_diag(dmrg_heff* H, double* diag, void* stream) {
@@ -790,6 +834,7 @@ void dmrg_heff_free(dmrg_heff* H) {
     free_set(C, H->TMR);
     if (H->diag_region >= 0) C->arena.release(H->diag_region);
     if (H->f32_region >= 0) C->arena.release(H->f32_region);
+    if (H->part_region >= 0) C->arena.release(H->part_region);
     delete H;
 }
 

@@ -3,10 +3,11 @@
 // chain_kernel: the grouped, output-stationary sector-GEMM engine described
 // in kernels.hpp.  One 256-thread workgroup (4 waves of 64) owns one output
 // tile of up to 64*MT rows x 32 columns.  MFMA 16x16x4 (f64 or f32) tiles:
-// wave w owns row tiles w, w+4, ...; both 16-column tiles.  A and B
-// operands are staged through LDS in k-chunks of 16 with coalesced loads
-// (the loader walks the operand's contiguous dimension); the group
-// intermediate U (mu x 32) is parked in LDS as the B operand of X . U.
+// wave w owns row tiles w, w+4, ...; both 16-column tiles.  The operands of
+// A . B and of X . U go from global memory (L2 / MALL hits for the reused
+// sector blocks) straight into MFMA fragments, one 16-k chunk ahead of the
+// multiply; only the group intermediate U (mu x 32), needed by every output
+// row, passes through LDS, with one barrier pair per group.
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include "kernels.hpp"
@@ -33,9 +34,47 @@ template <> struct Mfma<float> {
     __device__ static constexpr int row(int lk, int v) { return 4 * lk + v; }
 };
 
-constexpr int KC = 16;            // k chunk staged per LDS round
-constexpr int LDA_S = KC + 1;     // LDS row stride of A / X tiles
-constexpr int LDU_S = kTN + 1;    // LDS row stride of B tiles and U
+constexpr int LDU_S = kTN + 1;    // LDS row stride of U
+
+// One MFMA k-step group covers 16 consecutive k.  Lane (r = l%16, g = l/16)
+// supplies k = k0 + 4g + s at step s (s = 0..3): the four k of one lane are
+// contiguous in a row-major operand, and any fixed permutation of k used by
+// both operands leaves the product unchanged.
+template <typename T>
+struct Frag {
+    T v[4];
+};
+
+// A fragment: rows row0..row0+15 of a (rows x K) operand, k0..k0+15.
+// PAT 0: lane group g holds k = k0 + 4g + s; PAT 1: k = k0 + g + 4s.
+template <typename T, int PAT = 0>
+__device__ inline Frag<T> load_a(const T* __restrict__ p, int ld, bool tr, int row, int rows, int k0,
+                                 int K, int g, T scale) {
+    Frag<T> f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = PAT == 0 ? k0 + 4 * g + s : k0 + g + 4 * s;
+        T x = 0;
+        if (row < rows && k < K) x = tr ? p[(int64_t)k * ld + row] : p[(int64_t)row * ld + k];
+        f.v[s] = scale * x;
+    }
+    return f;
+}
+
+// B fragment: column col of a (K x cols) operand, k0..k0+15
+template <typename T>
+__device__ inline Frag<T> load_b(const T* __restrict__ p, int ld, bool tr, int col, int cols, int k0,
+                                 int K, int g) {
+    Frag<T> f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = k0 + 4 * g + s;
+        T x = 0;
+        if (col < cols && k < K) x = tr ? p[(int64_t)col * ld + k] : p[(int64_t)k * ld + col];
+        f.v[s] = x;
+    }
+    return f;
+}
 
 template <typename T, int MT>
 __global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tasks,
@@ -44,8 +83,6 @@ __global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tas
                                                     Bases<T> B) {
     using V4 = typename Mfma<T>::v4;
     constexpr int RC = 64 * MT;
-    __shared__ T sA[RC * LDA_S];
-    __shared__ T sB[KC * LDU_S];
     __shared__ T sU[RC * LDU_S];
 
     const int tid = threadIdx.x;
@@ -65,7 +102,6 @@ __global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tas
     for (int g = tk.g0; g < tk.g1; ++g) {
         const Group gr = groups[g];
         const int mu = gr.mu;
-        const int murows = (mu + 15) & ~15;
         V4 U[MT][2];
 #pragma unroll
         for (int i = 0; i < MT; ++i)
@@ -93,8 +129,8 @@ __global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tas
                             const int row = 16 * rt + Mfma<T>::row(lk, v);
                             T val = 0;
                             if (row < mu && col < tk.n) {
-                                if (ida && idb)
-                                    val = (row == col) ? alpha : T(0);
+                                if (ida && idb)   // a_off: diagonal offset of the identity
+                                    val = (row + ct.a_off == col) ? alpha : T(0);
                                 else if (ida)
                                     val = alpha * (tb ? Bp[(int64_t)col * ct.ldb + row]
                                                       : Bp[(int64_t)row * ct.ldb + col]);
@@ -108,48 +144,50 @@ __global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tas
                 }
                 continue;
             }
+            // U += alpha A . B, operands straight from global memory with the
+            // next 16-k chunk prefetched while the current one is multiplied
             const int K = ct.k;
-            for (int k0 = 0; k0 < K; k0 += KC) {
-                __syncthreads();
-                for (int idx = tid; idx < murows * KC; idx += 256) {
-                    int r, kk;
-                    if (ta) { r = idx % murows; kk = idx / murows; }
-                    else    { r = idx / KC;     kk = idx % KC; }
-                    T val = 0;
-                    if (r < mu && k0 + kk < K)
-                        val = alpha * (ta ? Ap[(int64_t)(k0 + kk) * ct.lda + r]
-                                          : Ap[(int64_t)r * ct.lda + k0 + kk]);
-                    sA[r * LDA_S + kk] = val;
+            const int n = tk.n, c0 = tk.col0;
+            Frag<T> fa[MT], fb[2], na[MT], nb[2];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const int rt = wave + 4 * i;
+                if (16 * rt < mu) fa[i] = load_a(Ap, ct.lda, ta, 16 * rt + lr, mu, 0, K, lk, alpha);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) fb[j] = load_b(Bp, ct.ldb, tb, c0 + 16 * j + lr, n, 0, K, lk);
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                const int k1 = k0 + 16;
+                if (k1 < K) {
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) {
+                        const int rt = wave + 4 * i;
+                        if (16 * rt < mu) na[i] = load_a(Ap, ct.lda, ta, 16 * rt + lr, mu, k1, K, lk, alpha);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) nb[j] = load_b(Bp, ct.ldb, tb, c0 + 16 * j + lr, n, k1, K, lk);
                 }
-                for (int idx = tid; idx < KC * kTN; idx += 256) {
-                    int kk, j;
-                    if (tb) { kk = idx % KC;  j = idx / KC; }
-                    else    { kk = idx / kTN; j = idx % kTN; }
-                    const int col = tk.col0 + j;
-                    T val = 0;
-                    if (k0 + kk < K && col < tk.n)
-                        val = tb ? Bp[(int64_t)col * ct.ldb + k0 + kk]
-                                 : Bp[(int64_t)(k0 + kk) * ct.ldb + col];
-                    sB[kk * LDU_S + j] = val;
-                }
-                __syncthreads();
 #pragma unroll
                 for (int i = 0; i < MT; ++i) {
                     const int rt = wave + 4 * i;
                     if (16 * rt >= mu) continue;
 #pragma unroll
-                    for (int kk = 0; kk < KC; kk += 4) {
-                        const T a = sA[(16 * rt + lr) * LDA_S + kk + lk];
-                        const T b0 = sB[(kk + lk) * LDU_S + lr];
-                        const T b1 = sB[(kk + lk) * LDU_S + 16 + lr];
-                        U[i][0] = Mfma<T>::mma(a, b0, U[i][0]);
-                        U[i][1] = Mfma<T>::mma(a, b1, U[i][1]);
+                    for (int s = 0; s < 4; ++s) {
+                        U[i][0] = Mfma<T>::mma(fa[i].v[s], fb[0].v[s], U[i][0]);
+                        U[i][1] = Mfma<T>::mma(fa[i].v[s], fb[1].v[s], U[i][1]);
                     }
+                }
+                if (k1 < K) {
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) fa[i] = na[i];
+                    fb[0] = nb[0];
+                    fb[1] = nb[1];
                 }
             }
         }
 
         if (gr.flags & G_HAS_X) {
+            // U is shared by all output rows: park it in LDS
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
@@ -160,37 +198,48 @@ __global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tas
                     for (int v = 0; v < 4; ++v)
                         sU[(16 * rt + Mfma<T>::row(lk, v)) * LDU_S + 16 * j + lr] = U[i][j][v];
             }
+            __syncthreads();
             const int xbuf = gr.flags & 7;
             const bool tx = (gr.flags & G_TRANS_X) != 0;
             const T* Xp = B.p[xbuf] + gr.x_off + (int64_t)vec * B.vstride[xbuf];
             const T xc = (T)gr.x_coef;
             const int m = tk.m;
-            const int mrows = (m + 15) & ~15;
-            for (int k0 = 0; k0 < mu; k0 += KC) {
-                __syncthreads();
-                for (int idx = tid; idx < mrows * KC; idx += 256) {
-                    int r, kk;
-                    if (tx) { r = idx % mrows; kk = idx / mrows; }
-                    else    { r = idx / KC;    kk = idx % KC; }
-                    T val = 0;
-                    if (r < m && k0 + kk < mu)
-                        val = xc * (tx ? Xp[(int64_t)(k0 + kk) * gr.ldx + r]
-                                       : Xp[(int64_t)r * gr.ldx + k0 + kk]);
-                    sA[r * LDA_S + kk] = val;
+            Frag<T> fx[MT], nx[MT];
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const int rt = wave + 4 * i;
+                if (16 * rt < m) fx[i] = load_a(Xp, gr.ldx, tx, 16 * rt + lr, m, 0, mu, lk, xc);
+            }
+            for (int k0 = 0; k0 < mu; k0 += 16) {
+                const int k1 = k0 + 16;
+                if (k1 < mu) {
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) {
+                        const int rt = wave + 4 * i;
+                        if (16 * rt < m) nx[i] = load_a(Xp, gr.ldx, tx, 16 * rt + lr, m, k1, mu, lk, xc);
+                    }
                 }
-                __syncthreads();
+                T b0[4], b1[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    // rows of U at or beyond mu are zero in LDS (their U tiles were zero)
+                    const int kr = k0 + 4 * lk + s;
+                    b0[s] = sU[kr * LDU_S + lr];
+                    b1[s] = sU[kr * LDU_S + 16 + lr];
+                }
 #pragma unroll
                 for (int i = 0; i < MT; ++i) {
                     const int rt = wave + 4 * i;
                     if (16 * rt >= m) continue;
 #pragma unroll
-                    for (int kk = 0; kk < KC; kk += 4) {
-                        const T a = sA[(16 * rt + lr) * LDA_S + kk + lk];
-                        const T b0 = sU[(k0 + kk + lk) * LDU_S + lr];
-                        const T b1 = sU[(k0 + kk + lk) * LDU_S + 16 + lr];
-                        acc[i][0] = Mfma<T>::mma(a, b0, acc[i][0]);
-                        acc[i][1] = Mfma<T>::mma(a, b1, acc[i][1]);
+                    for (int s = 0; s < 4; ++s) {
+                        acc[i][0] = Mfma<T>::mma(fx[i].v[s], b0[s], acc[i][0]);
+                        acc[i][1] = Mfma<T>::mma(fx[i].v[s], b1[s], acc[i][1]);
                     }
+                }
+                if (k1 < mu) {
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) fx[i] = nx[i];
                 }
             }
         }
@@ -203,9 +252,10 @@ __global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tas
         }
     }
 
-    const int cbuf = tk.cbuf & 7;
+    const int cbuf = tk.cbuf & 15;
     const bool accum = (tk.cbuf >> 8) & 1;
-    T* Cp = B.p[cbuf] + tk.c_off + (int64_t)vec * B.vstride[cbuf];
+    const int cshift = ((tk.cbuf >> 9) & 1) ? tk.col0 : 0;   // partial tiles store columns from 0
+    T* Cp = B.p[cbuf] + tk.c_off - cshift + (int64_t)vec * B.vstride[cbuf];
 #pragma unroll
     for (int i = 0; i < MT; ++i) {
         const int rt = wave + 4 * i;
@@ -226,27 +276,216 @@ __global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tas
     }
 }
 
+// Wave-per-task variant for tiles of at most 16*RT rows: each wave owns a whole
+// output tile (RT row tiles x 2 column tiles) and a whole group intermediate
+// U, so no LDS and no barrier is needed.  The accumulator layout of U is used
+// directly as the B operand of X . U: MFMA step (t, v) takes from lane group g
+// the U row held in register v of row tile t, and X is loaded with the same k
+// order (f32: k = 16t + 4g + v, f64: k = 16t + 4v + g).
+template <typename T, int RT>
+__global__ __launch_bounds__(256) void chain_wave_kernel(const Task* __restrict__ tasks, int ntask,
+                                                         const Group* __restrict__ groups,
+                                                         const Contrib* __restrict__ contribs,
+                                                         Bases<T> B) {
+    using V4 = typename Mfma<T>::v4;
+    constexpr int XPAT = Mfma<T>::row(1, 0) == 4 ? 0 : 1;   // f32: rows 4g+v; f64: rows 4v+g
+    const int lane = threadIdx.x & 63;
+    const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ti >= ntask) return;
+    const int lr = lane & 15;
+    const int lk = lane >> 4;
+    const Task tk = tasks[ti];
+    const int vec = blockIdx.y;
+
+    V4 acc[RT][2];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
+
+    for (int g = tk.g0; g < tk.g1; ++g) {
+        const Group gr = groups[g];
+        const int mu = gr.mu;
+        V4 U[RT][2];
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) U[i][j] = V4{0, 0, 0, 0};
+
+        for (int c = gr.c0; c < gr.c1; ++c) {
+            const Contrib ct = contribs[c];
+            const int abuf = ct.flags & 7, bbuf = (ct.flags >> 3) & 7;
+            const T* Ap = B.p[abuf] + ct.a_off + (int64_t)vec * B.vstride[abuf];
+            const T* Bp = B.p[bbuf] + ct.b_off + (int64_t)vec * B.vstride[bbuf];
+            const T alpha = (T)ct.alpha;
+            const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
+            if (ct.flags & (F_ID_A | F_ID_B)) {
+                const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
+#pragma unroll
+                for (int i = 0; i < RT; ++i) {
+                    if (16 * i >= mu) continue;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int col = tk.col0 + 16 * j + lr;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 16 * i + Mfma<T>::row(lk, v);
+                            T val = 0;
+                            if (row < mu && col < tk.n) {
+                                if (ida && idb)
+                                    val = (row + ct.a_off == col) ? alpha : T(0);
+                                else if (ida)
+                                    val = alpha * (tb ? Bp[(int64_t)col * ct.ldb + row]
+                                                      : Bp[(int64_t)row * ct.ldb + col]);
+                                else
+                                    val = alpha * (ta ? Ap[(int64_t)col * ct.lda + row]
+                                                      : Ap[(int64_t)row * ct.lda + col]);
+                            }
+                            U[i][j][v] += val;
+                        }
+                    }
+                }
+                continue;
+            }
+            const int K = ct.k;
+            const int n = tk.n, c0 = tk.col0;
+            const int nrt = (mu + 15) >> 4;
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                Frag<T> fb0 = load_b(Bp, ct.ldb, tb, c0 + lr, n, k0, K, lk);
+                Frag<T> fb1 = load_b(Bp, ct.ldb, tb, c0 + 16 + lr, n, k0, K, lk);
+                Frag<T> fa[RT];
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+                    if (i < nrt) fa[i] = load_a(Ap, ct.lda, ta, 16 * i + lr, mu, k0, K, lk, alpha);
+#pragma unroll
+                for (int i = 0; i < RT; ++i) {
+                    if (i >= nrt) continue;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        U[i][0] = Mfma<T>::mma(fa[i].v[s], fb0.v[s], U[i][0]);
+                        U[i][1] = Mfma<T>::mma(fa[i].v[s], fb1.v[s], U[i][1]);
+                    }
+                }
+            }
+        }
+
+        if (gr.flags & G_HAS_X) {
+            const int xbuf = gr.flags & 7;
+            const bool tx = (gr.flags & G_TRANS_X) != 0;
+            const T* Xp = B.p[xbuf] + gr.x_off + (int64_t)vec * B.vstride[xbuf];
+            const T xc = (T)gr.x_coef;
+            const int m = tk.m;
+            const int nmt = (m + 15) >> 4;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                if (16 * t >= mu) continue;
+                Frag<T> fx[RT];
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+                    if (i < nmt) fx[i] = load_a<T, XPAT>(Xp, gr.ldx, tx, 16 * i + lr, m, 16 * t, mu, lk, xc);
+#pragma unroll
+                for (int i = 0; i < RT; ++i) {
+                    if (i >= nmt) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        acc[i][0] = Mfma<T>::mma(fx[i].v[v], U[t][0][v], acc[i][0]);
+                        acc[i][1] = Mfma<T>::mma(fx[i].v[v], U[t][1][v], acc[i][1]);
+                    }
+                }
+            }
+        }
+        if (gr.xid_coef != 0.0) {
+            const T xi = (T)gr.xid_coef;
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] += xi * U[i][j];
+        }
+    }
+
+    const int cbuf = tk.cbuf & 15;
+    const bool accum = (tk.cbuf >> 8) & 1;
+    const int cshift = ((tk.cbuf >> 9) & 1) ? tk.col0 : 0;   // partial tiles store columns from 0
+    T* Cp = B.p[cbuf] + tk.c_off - cshift + (int64_t)vec * B.vstride[cbuf];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        if (16 * i >= tk.m) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = tk.col0 + 16 * j + lr;
+            if (col >= tk.n) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * i + Mfma<T>::row(lk, v);
+                if (row < tk.m) {
+                    T* d = Cp + (int64_t)row * tk.ldc + col;
+                    *d = accum ? *d + acc[i][j][v] : acc[i][j][v];
+                }
+            }
+        }
+    }
+}
+
 template <typename T>
-static int launch_chain(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+static int launch_chain(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
                         const Bases<T>& b, int nvec, void* stream) {
     if (ntask <= 0) return 0;
     dim3 grid(ntask, nvec), block(256);
     hipStream_t s = (hipStream_t)stream;
-    switch (cls) {
-        case 0: hipLaunchKernelGGL((chain_kernel<T, 1>), grid, block, 0, s, t, g, c, b); break;
-        case 1: hipLaunchKernelGGL((chain_kernel<T, 2>), grid, block, 0, s, t, g, c, b); break;
-        default: hipLaunchKernelGGL((chain_kernel<T, 5>), grid, block, 0, s, t, g, c, b); break;
-    }
+    dim3 wgrid((ntask + 3) / 4, nvec);
+    if (variant == 1 && cls == 0)
+        hipLaunchKernelGGL((chain_wave_kernel<T, 4>), wgrid, block, 0, s, t, ntask, g, c, b);
+    else if (variant == 1 && cls == 1)
+        hipLaunchKernelGGL((chain_wave_kernel<T, 8>), wgrid, block, 0, s, t, ntask, g, c, b);
+    else if (cls == 0)
+        hipLaunchKernelGGL((chain_kernel<T, 1>), grid, block, 0, s, t, g, c, b);
+    else if (cls == 1)
+        hipLaunchKernelGGL((chain_kernel<T, 2>), grid, block, 0, s, t, g, c, b);
+    else
+        hipLaunchKernelGGL((chain_kernel<T, 5>), grid, block, 0, s, t, g, c, b);
     return (int)hipGetLastError();
 }
 
-int launch_chain_f64(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f64(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<double>& b, int nvec, void* stream) {
-    return launch_chain<double>(cls, t, ntask, g, c, b, nvec, stream);
+    return launch_chain<double>(cls, variant, t, ntask, g, c, b, nvec, stream);
 }
-int launch_chain_f32(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f32(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<float>& b, int nvec, void* stream) {
-    return launch_chain<float>(cls, t, ntask, g, c, b, nvec, stream);
+    return launch_chain<float>(cls, variant, t, ntask, g, c, b, nvec, stream);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_kernel(const Reduce* __restrict__ red, Bases<T> b) {
+    const Reduce r = red[blockIdx.x];
+    const int vec = blockIdx.y;
+    const int ncol = min(32, r.n - r.col0);
+    const int cbuf = r.cbuf & 15;
+    const bool accum = (r.cbuf >> 8) & 1;
+    const T* P = b.p[kPartialBuf] + r.poff + (int64_t)vec * b.vstride[kPartialBuf];
+    T* Cp = b.p[cbuf] + r.c_off + (int64_t)vec * b.vstride[cbuf];
+    const int64_t slot = (int64_t)r.m * 32;
+    for (int e = threadIdx.x; e < r.m * 32; e += blockDim.x) {
+        const int row = e >> 5, j = e & 31;
+        if (j >= ncol) continue;
+        T s = 0;
+        for (int q = 0; q < r.nslot; ++q) s += P[q * slot + e];
+        T* d = Cp + (int64_t)row * r.ldc + r.col0 + j;
+        *d = accum ? *d + s : s;
+    }
+}
+
+template <typename T>
+static int launch_reduce(const Reduce* r, int nred, const Bases<T>& b, int nvec, void* stream) {
+    if (nred <= 0) return 0;
+    hipLaunchKernelGGL(reduce_kernel<T>, dim3(nred, nvec), dim3(256), 0, (hipStream_t)stream, r, b);
+    return (int)hipGetLastError();
+}
+int launch_reduce_f64(const Reduce* r, int nred, const Bases<double>& b, int nvec, void* stream) {
+    return launch_reduce<double>(r, nred, b, nvec, stream);
+}
+int launch_reduce_f32(const Reduce* r, int nred, const Bases<float>& b, int nvec, void* stream) {
+    return launch_reduce<float>(r, nred, b, nvec, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,19 +661,23 @@ int launch_combine(const double* V, int nv, const double* C, int ldc, double* Y,
 }
 
 __global__ void precond_kernel(const double* __restrict__ r, const double* __restrict__ d,
-                               double theta, double* __restrict__ t, int64_t n) {
+                               double theta, double clamp, double* __restrict__ t, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
+        if (clamp < 0.0) {
+            t[i] = r[i];
+            continue;
+        }
         double den = theta - d[i];
-        if (fabs(den) < 1e-4) den = den < 0 ? -1e-4 : 1e-4;
+        if (fabs(den) < clamp) den = den < 0 ? -clamp : clamp;
         t[i] = r[i] / den;
     }
 }
 
-int launch_precond(const double* r, const double* d, double theta, double* t, int64_t n,
+int launch_precond(const double* r, const double* d, double theta, double clamp, double* t, int64_t n,
                    void* stream) {
     hipLaunchKernelGGL(precond_kernel, grid_for(n), dim3(256), 0, (hipStream_t)stream, r, d, theta,
-                       t, n);
+                       clamp, t, n);
     return (int)hipGetLastError();
 }
 

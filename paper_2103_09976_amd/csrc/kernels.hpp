@@ -23,7 +23,7 @@
 namespace dmrgk {
 
 constexpr int kTN = 32;          // output columns per task
-constexpr int kMaxBuf = 8;
+constexpr int kMaxBuf = 9;       // buffer 8: partial tiles of split tasks
 
 // flag bits
 enum : int32_t {
@@ -36,7 +36,7 @@ struct Task {          // one output tile
     int32_t ldc, m, n; // block rows, columns (tile covers columns col0..col0+31)
     int32_t col0;
     int32_t g0, g1;    // group range
-    int32_t cbuf;      // buffer id of C | (accumulate << 8)
+    int32_t cbuf;      // buffer id of C (bits 0-3) | accumulate << 8 | tile-local columns << 9
 };
 
 struct Group {
@@ -65,11 +65,28 @@ struct Bases {
 constexpr int kNumClass = 3;
 constexpr int kClassRows[kNumClass] = {64, 128, 320};
 
+// Kernel variants per row class: 0 = four waves cooperate on one tile (U shared
+// through LDS), 1 = one wave per tile (U in registers; classes 0 and 1 only).
+constexpr int kNumVariant = 2;
+
 // launchers (return hipError_t as int)
-int launch_chain_f64(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f64(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<double>& b, int nvec, void* stream);
-int launch_chain_f32(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f32(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<float>& b, int nvec, void* stream);
+
+// A task whose group range is split writes each chunk's tile to its own slot
+// of the partial buffer (tile-local: ldc = 32, columns from 0); the slots are
+// then summed in slot order, so the result does not depend on scheduling:
+//   C[r][col0 + j] (+)= sum_{s < nslot} P[poff + s*m*32 + r*32 + j]
+constexpr int kPartialBuf = 8;
+struct Reduce {
+    int64_t c_off, poff;
+    int32_t ldc, m, n, col0, nslot;
+    int32_t cbuf;      // buffer id of C | accumulate << 8
+};
+int launch_reduce_f64(const Reduce* r, int nred, const Bases<double>& b, int nvec, void* stream);
+int launch_reduce_f32(const Reduce* r, int nred, const Bases<float>& b, int nvec, void* stream);
 
 int launch_cast_d2f(const double* in, float* out, int64_t n, void* stream);
 int launch_cast_f2d(const float* in, double* out, int64_t n, void* stream);
@@ -88,8 +105,8 @@ int launch_gram(const double* V, int nv, const double* W, int nw, int64_t n,
 // Y_j = sum_i C[i*ldc + j] V_i (+ beta Y_j) for j < ny
 int launch_combine(const double* V, int nv, const double* C, int ldc, double* Y, int ny,
                    int64_t n, double beta, void* stream);
-// t = r / clamp(theta - d)   (preconditioned residual)
-int launch_precond(const double* r, const double* d, double theta, double* t, int64_t n,
+// t = r / (theta - d) with |theta - d| >= clamp; clamp < 0: t = r
+int launch_precond(const double* r, const double* d, double theta, double clamp, double* t, int64_t n,
                    void* stream);
 // symmetric eigen-decomposition of an n x n matrix (n <= 64), one workgroup,
 // cyclic Jacobi; A row-major in, eigenvalues ascending in w, eigenvectors as

@@ -40,7 +40,8 @@ class Bsm(C.Structure):
 
 class DavOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("max_subspace", C.c_int32), ("tol", C.c_double),
-                ("precision", C.c_int32), ("switch_tol", C.c_double), ("fixed_iters", C.c_int32)]
+                ("precision", C.c_int32), ("switch_tol", C.c_double), ("fixed_iters", C.c_int32),
+                ("precond_clamp", C.c_double)]
 
 
 class DavStats(C.Structure):
@@ -202,11 +203,11 @@ class Heff:
 
     def davidson(self, psi, n_roots: int = 1, tol: float = 1e-6, max_iter: int = 300,
                  max_subspace: int = 24, precision: int = DMRG_PREC_F64, switch_tol: float = 1e-4,
-                 fixed_iters: int = 0):
+                 fixed_iters: int = 0, precond_clamp: float = 0.0):
         import torch
         assert psi.dtype == torch.float64 and psi.numel() >= n_roots * self.dim
         e = (C.c_double * n_roots)()
-        opts = DavOpts(max_iter, max_subspace, tol, precision, switch_tol, fixed_iters)
+        opts = DavOpts(max_iter, max_subspace, tol, precision, switch_tol, fixed_iters, precond_clamp)
         st = DavStats()
         _check(load().dmrg_davidson(self.ptr, n_roots, C.c_void_p(psi.data_ptr()), e, C.byref(opts),
                                     C.byref(st), _stream(torch)))
