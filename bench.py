@@ -24,6 +24,38 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "Hψ TFLOP/s + ms/Davidson iter, FP32-mixed vs FP64, at |ΔE|≤1e-8 Eh"
+KERNEL_SRC = os.path.join(ROOT, "paper_2103_09976_amd", "csrc", "kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def launch_kernel_name(kind: int, prec: str = "float") -> str:
+    """Kernel of launch slot `kind` of one H_eff product (see dmrg_heff_profile)."""
+    if kind < 6:
+        return f"tile_kernel<{prec}, {kind + 1}>"
+    if kind < 10:
+        rt, ct = divmod(kind - 6, 2)
+        return f"wave_kernel<{prec}, {rt + 1}, {ct + 1}>"
+    return f"reduce_kernel<{prec}>"
+
+
+def counted_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration), or None when
+    the summary is missing or was taken on another version of the kernel source."""
+    import hashlib
+    path = os.path.join(PROFILES, f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    lines = open(path).read().splitlines()
+    if not any(l.strip() == f"kernels.hip sha256: {sha}" for l in lines):
+        return None
+    for l in lines:
+        if l.startswith("kernel: ") and f"name={kernel};" in l:
+            for f in l.split(";"):
+                if f.strip().startswith("hbm_bytes_per_launch="):
+                    return int(float(f.split("=")[1]))
+    return None
 PEAK = {"f32": 157.3, "f64": 78.6}     # MI355X dense MFMA, TFLOP/s
 HBM_PEAK = 8000.0                       # GB/s
 
@@ -128,8 +160,25 @@ def main():
     if args.profile_apply:
         L, R, H = build()
         ts = timed_apply(H, dmrg.DMRG_PREC_F32, args.profile_apply)
-        print(json.dumps({"profile_apply_ms": ts, "flops": H.flops}), flush=True)
+        ts64 = timed_apply(H, dmrg.DMRG_PREC_F64, args.profile_apply)
+        # calibration for the HBM byte counters: a plain copy of 1 GiB (read 1 GiB, write 1 GiB)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_apply_ms_f32": ts, "profile_apply_ms_f64": ts64, "flops": H.flops,
+                          "copy_bytes_each_way": src.numel() * 4}), flush=True)
         return
+
+    def launch_profile(H):
+        x, y = x32[:dim], y32[:dim]
+        H.apply(x, y, dmrg.DMRG_PREC_F32)
+        runs = [H.profile(x, y, dmrg.DMRG_PREC_F32) for _ in range(3)]
+        out = []
+        for i, (kind, _, fl) in enumerate(runs[0]):
+            out.append((kind, float(np.median([r[i][1] for r in runs])), fl))
+        return out
 
     def step(record):
         t0 = time.perf_counter()
@@ -146,7 +195,8 @@ def main():
         t1 = time.perf_counter()
         rec = dict(ms_step=(t1 - t0) * 1e3, ms_build=(tb - t0) * 1e3, ms_davidson=(td - tb) * 1e3,
                    dav=st, energies=e.tolist(), t32=t32, t64=t64, flops=H.flops, bytes32=H.bytes(1),
-                   bytes64=H.bytes(0), terms=H.terms(), arena_peak=ctx.arena_peak)
+                   bytes64=H.bytes(0), terms=H.terms(), arena_peak=ctx.arena_peak,
+                   launches=launch_profile(H))
         if record is not None:
             record.append(rec)
         last = (H, L, R, N)
@@ -212,14 +262,14 @@ def main():
         "dE_mixed_vs_f64": dE,
         "davidson_iters": dav["iters"],
         "F_alg_per_vector": recs[-1]["flops"],
+        "hpsi_algorithmic_bytes_f32": recs[-1]["bytes32"],
+        "hpsi_algorithmic_GBps_f32": round(recs[-1]["bytes32"] / (t32 * 1e-3) / 1e9, 1),
         "terms_2idx_1idx_H": recs[-1]["terms"],
         "ms_build": round(float(np.median([r["ms_build"] for r in recs])), 1),
         "arena_peak_gb": round(recs[-1]["arena_peak"] / 2**30, 2),
-        "roofline": {"bound": "mfma", "achieved": round(tf32, 3), "peak": PEAK["f32"], "unit": "TFLOP/s",
-                     "frac": round(tf32 / PEAK["f32"], 4), "traffic": None,
-                     "kernel": "chain_kernel<float> (all row classes of one H_eff psi)",
-                     "algorithmic_bytes": recs[-1]["bytes32"],
-                     "algorithmic_GBps": round(recs[-1]["bytes32"] / (t32 * 1e-3) / 1e9, 1)},
+        "roofline": roofline(recs[-1], args.workload),
+        "launches_f32": [{"kernel": launch_kernel_name(k), "ms": round(ms, 3), "useful_tflop": round(fl / 1e12, 4)}
+                         for k, ms, fl in recs[-1]["launches"] if ms > 0],
     }
     for o in last:
         o.free()
@@ -236,6 +286,23 @@ def main():
                                "sample": f"one H_eff psi of the 24-orbital M=500 workload (NumPy FP64), {dt:.2f} s; "
                                          f"host {platform.processor() or platform.machine()}, os.cpu_count={os.cpu_count()}"}
     print(json.dumps(out), flush=True)
+
+
+def roofline(rec, workload):
+    """Roofline of the dominant kernel (the longest launch of one FP32 H_eff product,
+    timed live with HIP events on the launch stream).  Its algorithmic flops are its
+    share of F_alg: the useful MFMA flops of its tiles, scaled so that the shares of all
+    launches sum to F_alg."""
+    la = rec["launches"]
+    useful = sum(fl for _, _, fl in la)
+    kind, ms, fl = max(la, key=lambda r: r[1])
+    alg = fl * rec["flops"] / useful
+    achieved = alg / (ms * 1e-3) / 1e12
+    name = launch_kernel_name(kind)
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f32"], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK["f32"], 4), "traffic": counted_traffic(workload, name),
+            "kernel": name, "ms_per_launch": round(ms, 3), "algorithmic_flops_per_launch": int(alg),
+            "launch_share_of_hpsi_time": round(ms / sum(r[1] for r in la), 3)}
 
 
 def _c2_flops():

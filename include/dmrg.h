@@ -192,6 +192,19 @@ int64_t dmrg_heff_bytes(const dmrg_heff* H, int32_t precision);
 /* number of H_eff terms (two-index, one-index, block Hamiltonians) */
 int32_t dmrg_heff_terms(const dmrg_heff* H, int32_t* n2, int32_t* n1, int32_t* nh);
 
+/* Kernel launches of one H_eff psi product (as dmrg_heff_apply with n_vec =
+ * 1), timed one by one with HIP events recorded on `stream` around each
+ * launch.  For launch i < n (n >= DMRG_HEFF_LAUNCHES): ms[i] = its duration,
+ * flops[i] = the useful MFMA flops of its tiles (2*m*mu*cols per X.U and
+ * 2*mu*k*cols per A.B, padding and identities excluded), kind[i] = kernel
+ * kind (0..5: LDS tile kernel with 1..6 waves, 6..9: one-wave kernel with
+ * (rows, cols) tiles of (16,16), (16,32), (32,16), (32,32), 10: partial-tile
+ * reduction).  Launches with no work report ms = 0.  Synchronizes `stream`.
+ * Returns the number of launches (>= 0) or a negative dmrg_status. */
+#define DMRG_HEFF_LAUNCHES 11
+int32_t dmrg_heff_profile(dmrg_heff* H, int32_t precision, const void* psi, void* sigma, int32_t n, float* ms,
+                          double* flops, int32_t* kind, void* stream);
+
 /* Sector metadata of an operator set's basis (host arrays of capacity
  * >= n): returns the sector count; fills qn[2*i], dims[i] when non-null. */
 int32_t dmrg_opset_basis(const dmrg_opset* s, int32_t n, int32_t* qn, int64_t* dims);

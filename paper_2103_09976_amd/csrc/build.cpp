@@ -414,7 +414,6 @@ static dmrg_status renormalize_ops(Ctx* C, const OpSetImpl& old, const OpSetImpl
             const int kq = S.ket[b], kb = S.bra[b];
             const int mq = nb.m[kq], mqb = nb.m[kb];
             const int g0 = (int)wl.groups.size();
-            int maxmu = 0;
             for (auto& kv : bucket) {
                 const int sb = kv.first.first, sk = kv.first.second;
                 const int a = ob.find(nb.q[kq] - kSiteQ[sk]);
@@ -452,13 +451,10 @@ static dmrg_status renormalize_ops(Ctx* C, const OpSetImpl& old, const OpSetImpl
                     wl.contribs.push_back(c);
                 }
                 g.c1 = (int)wl.contribs.size();
-                if (g.c1 > g.c0) {
-                    wl.groups.push_back(g);
-                    maxmu = std::max(maxmu, g.mu);
-                }
+                if (g.c1 > g.c0) wl.groups.push_back(g);
             }
             emit_block_tasks(wl, 3, F.base + (int64_t)fi.second * F.stride + S.off[b], mq, mqb, mq, g0,
-                             (int)wl.groups.size(), maxmu);
+                             (int)wl.groups.size());
         }
     }
     int64_t sz[dmrgk::kMaxBuf] = {0};

@@ -388,36 +388,38 @@ size_t WorkList::ntasks() const {
     return n;
 }
 
-int row_class(int rows) {
-    for (int c = 0; c < dmrgk::kNumClass; ++c)
-        if (rows <= dmrgk::kClassRows[c]) return c;
-    return -1;
+int task_class_of(const WorkList& w, const dmrgk::Task& t) {
+    int rows = t.m;
+    for (int g = t.g0; g < t.g1; ++g) rows = std::max(rows, w.groups[g].mu);
+    return dmrgk::task_class(rows, t.ncol);
 }
 
 void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int n, int g0, int g1,
-                      int maxrows, bool accumulate) {
+                      bool accumulate) {
     if (m <= 0 || n <= 0) return;
-    int cls = row_class(std::max(m, maxrows));
-    if (cls < 0) cls = dmrgk::kNumClass - 1;   // caller checks limits beforehand
-    for (int col0 = 0; col0 < n; col0 += dmrgk::kTN) {
-        dmrgk::Task t;
+    // near-equal column tiles of at most kMaxCols, widths in multiples of 16
+    const int nt = (n + dmrgk::kMaxCols - 1) / dmrgk::kMaxCols;
+    const int width = ((n + nt - 1) / nt + 15) / 16 * 16;
+    for (int col0 = 0; col0 < n; col0 += width) {
+        dmrgk::Task t{};
         t.c_off = c_off;
         t.ldc = ldc;
         t.m = m;
         t.n = n;
         t.col0 = col0;
+        t.ncol = std::min(width, n - col0);
         t.g0 = g0;
         t.g1 = g1;
         t.cbuf = cbuf | (accumulate ? 256 : 0);
-        w.task[cls].push_back(t);
+        w.task[task_class_of(w, t)].push_back(t);
     }
 }
 
-// Tiles taller than the largest row class (320) are split exactly: output
-// rows into row tiles, the inner dimension mu of X . U into chunks (a group
-// becomes one group per chunk; its identity part follows the output rows).
+// Tiles taller than kMaxRows are split exactly: output rows into row tiles,
+// the inner dimension mu of X . U into chunks (a group becomes one group per
+// chunk; its identity part follows the output rows).
 void split_large(WorkList& w) {
-    const int CAP = dmrgk::kClassRows[dmrgk::kNumClass - 1];
+    const int CAP = dmrgk::kMaxRows;
     bool need = false;
     for (auto& T : w.task)
         for (const dmrgk::Task& t : T) {
@@ -445,9 +447,7 @@ void split_large(WorkList& w) {
         bool big = t.m > CAP;
         for (int g = t.g0; g < t.g1 && !big; ++g) big = w.groups[g].mu > CAP;
         if (!big) {
-            int mx = t.m;
-            for (int g = t.g0; g < t.g1; ++g) mx = std::max(mx, w.groups[g].mu);
-            w.task[row_class(mx)].push_back(t);
+            w.task[task_class_of(w, t)].push_back(t);
             continue;
         }
         for (int r0 = 0; r0 < t.m; r0 += CAP) {
@@ -489,9 +489,9 @@ void split_large(WorkList& w) {
             u.m = rm;
             u.g0 = it->second.first;
             u.g1 = it->second.second;
-            int mx = rm;
-            for (int g = u.g0; g < u.g1; ++g) mx = std::max(mx, ng[g].mu);
-            w.task[row_class(mx)].push_back(u);
+            int rows = u.m;
+            for (int g = u.g0; g < u.g1; ++g) rows = std::max(rows, ng[g].mu);
+            w.task[dmrgk::task_class(rows, u.ncol)].push_back(u);
         }
     }
     w.groups.swap(ng);
@@ -501,20 +501,35 @@ void split_large(WorkList& w) {
 // Cost model of one group for a tile of m rows: MFMA work of the A.B
 // products and of X.U, plus a fixed per-group and per-contribution overhead
 // (fragment loads, the LDS round trip of U, barriers) in flop equivalents.
-static double group_cost(const WorkList& w, const dmrgk::Group& G, int m) {
+static double group_cost(const WorkList& w, const dmrgk::Group& G, int m, int ncol) {
+    const int cols = (ncol + 15) / 16 * 16;
     double f = 16384.0;
-    if (G.flags & dmrgk::G_HAS_X) f += 2.0 * m * G.mu * dmrgk::kTN;
+    if (G.flags & dmrgk::G_HAS_X) f += 2.0 * m * G.mu * cols;
     for (int c = G.c0; c < G.c1; ++c) {
         const dmrgk::Contrib& q = w.contribs[c];
         f += 4096.0;
-        if (!(q.flags & (dmrgk::F_ID_A | dmrgk::F_ID_B))) f += 2.0 * G.mu * q.k * dmrgk::kTN;
+        if (!(q.flags & (dmrgk::F_ID_A | dmrgk::F_ID_B))) f += 2.0 * G.mu * q.k * cols;
+    }
+    return f;
+}
+
+double task_useful_flops(const WorkList& w, const dmrgk::Task& t) {
+    const int cols = std::min(t.ncol, t.n - t.col0);
+    double f = 0;
+    for (int g = t.g0; g < t.g1; ++g) {
+        const dmrgk::Group& G = w.groups[g];
+        if (G.flags & dmrgk::G_HAS_X) f += 2.0 * t.m * G.mu * cols;
+        for (int c = G.c0; c < G.c1; ++c) {
+            const dmrgk::Contrib& q = w.contribs[c];
+            if (!(q.flags & (dmrgk::F_ID_A | dmrgk::F_ID_B))) f += 2.0 * G.mu * q.k * cols;
+        }
     }
     return f;
 }
 
 double task_cost(const WorkList& w, const dmrgk::Task& t) {
     double f = 0;
-    for (int g = t.g0; g < t.g1; ++g) f += group_cost(w, w.groups[g], t.m);
+    for (int g = t.g0; g < t.g1; ++g) f += group_cost(w, w.groups[g], t.m, t.ncol);
     return f;
 }
 
@@ -531,12 +546,10 @@ void balance_work(WorkList& w, int target_tasks) {
         for (const dmrgk::Task& t : T) {
             gc.resize(t.g1 - t.g0);
             double tc = 0;
-            for (int g = t.g0; g < t.g1; ++g) tc += gc[g - t.g0] = group_cost(w, w.groups[g], t.m);
+            for (int g = t.g0; g < t.g1; ++g) tc += gc[g - t.g0] = group_cost(w, w.groups[g], t.m, t.ncol);
             const int nchunk = (int)std::min<double>(std::ceil(tc / cap), t.g1 - t.g0);
             if (nchunk <= 1) {
-                int mx = t.m;
-                for (int g = t.g0; g < t.g1; ++g) mx = std::max(mx, w.groups[g].mu);
-                out[row_class(mx)].emplace_back(tc, t);
+                out[task_class_of(w, t)].emplace_back(tc, t);
                 continue;
             }
             // greedy cut at multiples of tc / nchunk
@@ -544,7 +557,7 @@ void balance_work(WorkList& w, int target_tasks) {
             int slot = 0;
             int a = t.g0;
             double run = 0, done = 0;
-            const int64_t slot_elems = (int64_t)t.m * dmrgk::kTN;
+            const int64_t slot_elems = (int64_t)t.m * t.ncol;
             for (int g = t.g0; g < t.g1; ++g) {
                 run += gc[g - t.g0];
                 const bool last = g + 1 == t.g1;
@@ -553,11 +566,9 @@ void balance_work(WorkList& w, int target_tasks) {
                 u.g0 = a;
                 u.g1 = g + 1;
                 u.c_off = poff + slot * slot_elems;
-                u.ldc = dmrgk::kTN;
+                u.ldc = t.ncol;
                 u.cbuf = dmrgk::kPartialBuf | (1 << 9);
-                int mx = t.m;
-                for (int h = u.g0; h < u.g1; ++h) mx = std::max(mx, w.groups[h].mu);
-                out[row_class(mx)].emplace_back(run, u);
+                out[task_class_of(w, u)].emplace_back(run, u);
                 done += run;
                 run = 0;
                 a = g + 1;
@@ -568,8 +579,8 @@ void balance_work(WorkList& w, int target_tasks) {
             r.poff = poff;
             r.ldc = t.ldc;
             r.m = t.m;
-            r.n = t.n;
             r.col0 = t.col0;
+            r.ncol = t.ncol;
             r.nslot = slot;
             r.cbuf = t.cbuf & (15 | 256);
             w.reduces.push_back(r);
@@ -593,14 +604,14 @@ dmrg_status validate_work(WorkList& w, const int64_t* size) {
         return buf >= 0 && buf < dmrgk::kMaxBuf && first >= 0 && last < size[buf] && first <= last;
     };
     for (int cls = 0; cls < dmrgk::kNumClass; ++cls) {
-        const int cap = dmrgk::kClassRows[cls];
+        const int cap = dmrgk::class_rows(cls);
         int lg0 = -1, lg1 = -1;
         for (const dmrgk::Task& t : w.task[cls]) {
             const bool local = (t.cbuf >> 9) & 1;
-            if (t.m > cap || t.m < 1 || t.n < 1 || t.col0 < 0 || t.col0 >= t.n ||
-                (local ? t.ldc != dmrgk::kTN : t.ldc < t.n))
+            if (t.m > cap || t.m < 1 || t.n < 1 || t.col0 < 0 || t.ncol < 1 || t.col0 + t.ncol > t.n ||
+                t.ncol > dmrgk::class_cols(cls) || (local ? t.ldc != t.ncol : t.ldc < t.n))
                 return fail(DMRG_E_STATE, "work list: bad task shape");
-            if (local ? !in(t.cbuf & 15, t.c_off, t.c_off + (int64_t)t.m * dmrgk::kTN - 1)
+            if (local ? !in(t.cbuf & 15, t.c_off, t.c_off + (int64_t)t.m * t.ncol - 1)
                       : !in(t.cbuf & 15, t.c_off, t.c_off + (int64_t)(t.m - 1) * t.ldc + t.n - 1))
                 return fail(DMRG_E_STATE, "work list: output out of bounds");
             if (t.g0 == lg0 && t.g1 == lg1) continue;
@@ -655,11 +666,11 @@ dmrg_status validate_work(WorkList& w, const int64_t* size) {
         }
     }
     for (const dmrgk::Reduce& r : w.reduces) {
-        if (r.m < 1 || r.n < 1 || r.col0 < 0 || r.col0 >= r.n || r.ldc < r.n || r.nslot < 1)
+        if (r.m < 1 || r.ncol < 1 || r.col0 < 0 || r.col0 + r.ncol > r.ldc || r.nslot < 1)
             return fail(DMRG_E_STATE, "work list: bad reduction shape");
-        if (!in(r.cbuf & 15, r.c_off, r.c_off + (int64_t)(r.m - 1) * r.ldc + r.n - 1))
+        if (!in(r.cbuf & 15, r.c_off, r.c_off + (int64_t)(r.m - 1) * r.ldc + r.col0 + r.ncol - 1))
             return fail(DMRG_E_STATE, "work list: reduction output out of bounds");
-        if (!in(dmrgk::kPartialBuf, r.poff, r.poff + (int64_t)r.nslot * r.m * dmrgk::kTN - 1))
+        if (!in(dmrgk::kPartialBuf, r.poff, r.poff + (int64_t)r.nslot * r.m * r.ncol - 1))
             return fail(DMRG_E_STATE, "work list: partial tiles out of bounds");
     }
     return DMRG_OK;
@@ -686,6 +697,8 @@ dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
     for (int c = 0; c < dmrgk::kNumClass; ++c) {
         d.task[c] = (dmrgk::Task*)(base + toff[c]);
         d.ntask[c] = (int)w.task[c].size();
+        d.useful[c] = 0;
+        for (const dmrgk::Task& t : w.task[c]) d.useful[c] += task_useful_flops(w, t);
         if (!w.task[c].empty())
             DMRG_HIP(hipMemcpyAsync(d.task[c], w.task[c].data(), w.task[c].size() * sizeof(dmrgk::Task),
                                     hipMemcpyHostToDevice, s));
@@ -714,18 +727,53 @@ void free_work(Ctx* ctx, DevWork& d) {
 
 dmrg_status run_work_f64(const DevWork& d, const dmrgk::Bases<double>& b, int nvec, void* stream) {
     for (int c = dmrgk::kNumClass - 1; c >= 0; --c)
-        DMRG_HIP(dmrgk::launch_chain_f64(c, d.variant[c], d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec,
-                                         stream));
+        DMRG_HIP(dmrgk::launch_chain_f64(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec, stream));
     DMRG_HIP(dmrgk::launch_reduce_f64(d.reduces, d.nred, b, nvec, stream));
     return DMRG_OK;
 }
 
 dmrg_status run_work_f32(const DevWork& d, const dmrgk::Bases<float>& b, int nvec, void* stream) {
     for (int c = dmrgk::kNumClass - 1; c >= 0; --c)
-        DMRG_HIP(dmrgk::launch_chain_f32(c, d.variant[c], d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec,
-                                         stream));
+        DMRG_HIP(dmrgk::launch_chain_f32(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec, stream));
     DMRG_HIP(dmrgk::launch_reduce_f32(d.reduces, d.nred, b, nvec, stream));
     return DMRG_OK;
+}
+
+template <typename T, typename L, typename R>
+static dmrg_status run_timed(const DevWork& d, const dmrgk::Bases<T>& b, float* ms, void* stream, L chain, R red) {
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[2 * (dmrgk::kNumClass + 1)];
+    for (auto& e : ev) DMRG_HIP(hipEventCreate(&e));
+    dmrg_status st = DMRG_OK;
+    for (int c = dmrgk::kNumClass - 1; c >= 0 && st == DMRG_OK; --c) {   // classes high -> low, then reduce
+        hipEventRecord(ev[2 * c], s);
+        const int e = chain(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, 1, stream);
+        hipEventRecord(ev[2 * c + 1], s);
+        if (e) st = hip_fail(e, "kernel launch");
+    }
+    if (st == DMRG_OK) {
+        hipEventRecord(ev[2 * dmrgk::kNumClass], s);
+        const int e = red(d.reduces, d.nred, b, 1, stream);
+        hipEventRecord(ev[2 * dmrgk::kNumClass + 1], s);
+        if (e) st = hip_fail(e, "kernel launch");
+    }
+    if (st == DMRG_OK && hipEventSynchronize(ev[2 * dmrgk::kNumClass + 1]) != hipSuccess)
+        st = fail(DMRG_E_HIP, "event synchronize");
+    for (int c = 0; c <= dmrgk::kNumClass && st == DMRG_OK; ++c) {
+        const bool empty = c < dmrgk::kNumClass ? d.ntask[c] == 0 : d.nred == 0;
+        float t = 0;
+        if (!empty) hipEventElapsedTime(&t, ev[2 * c], ev[2 * c + 1]);
+        ms[c] = t;
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    return st;
+}
+
+dmrg_status run_work_timed_f64(const DevWork& d, const dmrgk::Bases<double>& b, float* ms, void* stream) {
+    return run_timed<double>(d, b, ms, stream, dmrgk::launch_chain_f64, dmrgk::launch_reduce_f64);
+}
+dmrg_status run_work_timed_f32(const DevWork& d, const dmrgk::Bases<float>& b, float* ms, void* stream) {
+    return run_timed<float>(d, b, ms, stream, dmrgk::launch_chain_f32, dmrgk::launch_reduce_f32);
 }
 
 // ---------------------------------------------------------------------------
@@ -796,7 +844,7 @@ dmrg_status family_gemm(Ctx* ctx, const std::vector<double>& W, const OpSetImpl&
         g.c1 = (int)wl.contribs.size();
         wl.groups.push_back(g);
         emit_block_tasks(wl, 3, D.base + (int64_t)(row0 + r0) * stride, (int)stride, rows, (int)stride,
-                         g0, g0 + 1, rows);
+                         g0, g0 + 1);
     }
     int64_t sz[dmrgk::kMaxBuf] = {0};
     sz[0] = (int64_t)W.size();

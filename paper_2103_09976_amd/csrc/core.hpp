@@ -222,16 +222,16 @@ struct WorkList {
 // device copy of a work list (in the arena)
 struct DevWork {
     int64_t region = -1;
-    dmrgk::Task* task[dmrgk::kNumClass] = {nullptr, nullptr, nullptr};
-    int ntask[dmrgk::kNumClass] = {0, 0, 0};
+    dmrgk::Task* task[dmrgk::kNumClass] = {};
+    int ntask[dmrgk::kNumClass] = {};
     dmrgk::Group* groups = nullptr;
     dmrgk::Contrib* contribs = nullptr;
     dmrgk::Reduce* reduces = nullptr;
     int nred = 0;
-    int variant[dmrgk::kNumClass] = {0, 0, 0};   // kernel variant per row class
+    double useful[dmrgk::kNumClass] = {};   // useful MFMA flops per class (one vector)
 };
 dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
-// splits tiles above 320 rows, then checks every operand of every task on the
+// splits tiles above kMaxRows rows, then checks every operand of every task on the
 // host; size[b] = elements of buffer b
 dmrg_status validate_work(WorkList& w, const int64_t* size);
 void split_large(WorkList& w);
@@ -240,14 +240,20 @@ void split_large(WorkList& w);
 // reduction sums in fixed order), then orders every class by decreasing cost.
 void balance_work(WorkList& w, int target_tasks);
 double task_cost(const WorkList& w, const dmrgk::Task& t);
+// class of a task: by its columns and the largest of its rows and group mu
+int task_class_of(const WorkList& w, const dmrgk::Task& t);
 void free_work(Ctx* ctx, DevWork& d);
-int row_class(int rows);
 dmrg_status run_work_f64(const DevWork& d, const dmrgk::Bases<double>& b, int nvec, void* stream);
 dmrg_status run_work_f32(const DevWork& d, const dmrgk::Bases<float>& b, int nvec, void* stream);
+// as run_work_*, one vector, with HIP events around each launch: ms[c] for
+// class c, ms[kNumClass] for the reduction (0 for empty launches)
+dmrg_status run_work_timed_f64(const DevWork& d, const dmrgk::Bases<double>& b, float* ms, void* stream);
+dmrg_status run_work_timed_f32(const DevWork& d, const dmrgk::Bases<float>& b, float* ms, void* stream);
+double task_useful_flops(const WorkList& w, const dmrgk::Task& t);
 
 // emit the tasks of one output block (m x n at c_off) with the given group range
 void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int n, int g0, int g1,
-                      int maxrows, bool accumulate = false);
+                      bool accumulate = false);
 
 // ------------- weighted sums ------------------------------------------------
 // out (family in `temps`) = sum_k w_k * ops[k] of input family `fam` in `src`

@@ -39,11 +39,12 @@ struct PhaseClock {
 };
 
 // Number of equal-cost chunks the H_eff work is cut into (tasks above
-// total/target are split): enough for many workgroups per compute unit so
-// the last wave of the launch is short.  DMRG_BALANCE overrides it.
+// total/target are split): enough for many resident waves per compute unit
+// (the small-tile kernels hide latency by occupancy) and a short last wave
+// of each launch.  DMRG_BALANCE overrides it.
 static int balance_target() {
     const char* e = std::getenv("DMRG_BALANCE");
-    return e ? std::atoi(e) : 8192;
+    return e ? std::atoi(e) : 131072;
 }
 
 using namespace dmrg;
@@ -193,7 +194,7 @@ static dmrg_status materialize(Ctx* C, std::vector<TransOp*> ops, const OpSetImp
             int ng = 0;
             if (g.c1 > g.c0) { wl.groups.push_back(g); ng = 1; }
             emit_block_tasks(wl, 3, F.base + (int64_t)j.idx * F.stride + S.off[b], B.m[a], B.m[a2], B.m[a], g0,
-                             g0 + ng, B.m[a2]);
+                             g0 + ng);
         }
     }
     int64_t sz[dmrgk::kMaxBuf] = {0};
@@ -405,7 +406,6 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         for (size_t o = o0; o < o1; ++o) {
             const PsiBlock& O = H->blocks[o];
             const int g0 = (int)wl.groups.size();
-            int maxmu = 0;
             dmrgk::DiagBlock db{};
             db.off = O.off;
             db.ma = O.ma;
@@ -536,7 +536,6 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
                     g.c1 = (int)wl.contribs.size();
                     if (g.c1 == g.c0) continue;
                     wl.groups.push_back(g);
-                    maxmu = std::max(maxmu, g.mu);
                     if (S.x) {
                         Lc.rfx[t] += 2.0 * O.ma * lb.m[a] * O.mb;
                         note(xb, S.off, (int64_t)O.ma * lb.m[a]);
@@ -552,7 +551,7 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
             }
             db.c1 = (int)Lc.dtm.size();
             Lc.dbl.push_back(db);
-            emit_block_tasks(wl, 3, O.off, O.mb, O.ma, O.mb, g0, (int)wl.groups.size(), maxmu);
+            emit_block_tasks(wl, 3, O.off, O.mb, O.ma, O.mb, g0, (int)wl.groups.size());
         }
     };
     const size_t nblk = H->blocks.size();
@@ -662,8 +661,6 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
     }
     dmrg_status st = upload_work(C, wl, H->work, stream);
     if (st != DMRG_OK) return st;
-    if (const char* v = std::getenv("DMRG_VARIANT"))   // per-class kernel variant, e.g. "110"
-        for (int c = 0; c < dmrgk::kNumClass && v[c]; ++c) H->work.variant[c] = (v[c] == '1' && c < 2) ? 1 : 0;
     clk.mark("upload");
     // diagonal lists
     {
@@ -794,6 +791,42 @@ dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec, cons
         if (st != DMRG_OK) return st;
     }
     return DMRG_OK;
+}
+
+int32_t dmrg_heff_profile(dmrg_heff* H, int32_t precision, const void* psi, void* sigma, int32_t n, float* ms,
+                          double* flops, int32_t* kind, void* stream) {
+    if (!H || !psi || !sigma || !ms || !flops || !kind) return fail(DMRG_E_ARG, "null argument");
+    if (psi == sigma) return fail(DMRG_E_ARG, "psi and sigma must not alias");
+    if (n < dmrgk::kNumClass + 1) return fail(DMRG_E_ARG, "n below DMRG_HEFF_LAUNCHES");
+    float t[dmrgk::kNumClass + 1] = {0};
+    dmrg_status st;
+    if (precision == DMRG_PREC_F64) {
+        dmrgk::Bases<double> b = bases64(H);
+        b.p[2] = (double*)psi;
+        b.p[3] = (double*)sigma;
+        b.vstride[2] = b.vstride[3] = H->dim;
+        st = run_work_timed_f64(H->work, b, t, stream);
+    } else if (precision == DMRG_PREC_F32) {
+        st = ensure_f32(H, stream);
+        if (st != DMRG_OK) return st;
+        dmrgk::Bases<float> b{};
+        for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
+        b.p[dmrgk::kPartialBuf] = H->part ? (float*)H->part : H->f32[0];
+        b.vstride[dmrgk::kPartialBuf] = H->part_elems;
+        b.p[2] = (float*)psi;
+        b.p[3] = (float*)sigma;
+        b.vstride[2] = b.vstride[3] = H->dim;
+        st = run_work_timed_f32(H->work, b, t, stream);
+    } else {
+        return fail(DMRG_E_ARG, "bad precision");
+    }
+    if (st != DMRG_OK) return st;
+    for (int i = 0; i <= dmrgk::kNumClass; ++i) {
+        ms[i] = t[i];
+        flops[i] = i < dmrgk::kNumClass ? H->work.useful[i] : 0.0;
+        kind[i] = i;
+    }
+    return dmrgk::kNumClass + 1;
 }
 
 dmrg_status dmrg_heff_diag(dmrg_heff* H, double* diag, void* stream) {

@@ -1,13 +1,15 @@
 // HIP kernels (gfx950) of the DMRG library.
 //
-// chain_kernel: the grouped, output-stationary sector-GEMM engine described
-// in kernels.hpp.  One 256-thread workgroup (4 waves of 64) owns one output
-// tile of up to 64*MT rows x 32 columns.  MFMA 16x16x4 (f64 or f32) tiles:
-// wave w owns row tiles w, w+4, ...; both 16-column tiles.  The operands of
-// A . B and of X . U go from global memory (L2 / MALL hits for the reused
-// sector blocks) straight into MFMA fragments, one 16-k chunk ahead of the
-// multiply; only the group intermediate U (mu x 32), needed by every output
-// row, passes through LDS, with one barrier pair per group.
+// tile_kernel: the grouped, output-stationary sector-GEMM engine described
+// in kernels.hpp.  A workgroup of NCT waves owns one output tile of up to 96
+// rows x 16*NCT columns; wave w owns the 16-column slice w of both the tile
+// and every group intermediate U.  Per group, U (mu x 16 per wave) is
+// accumulated in MFMA registers over the contributions and then used
+// directly as the B operand of X . U, so U never leaves the registers.  The
+// operands shared by all waves (the A_c and X rows) and the B_c columns of
+// the tile are staged through double-buffered LDS in chunks of 16 k with
+// coalesced global loads; the loads of the next chunk are in flight while
+// the MFMAs of the current one run.  MFMA 16x16x4 in f64 or f32.
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include "kernels.hpp"
@@ -34,364 +36,456 @@ template <> struct Mfma<float> {
     __device__ static constexpr int row(int lk, int v) { return 4 * lk + v; }
 };
 
-constexpr int LDU_S = kTN + 1;    // LDS row stride of U
+constexpr int kRT = kMaxRows / 16;   // row tiles of a task
+constexpr int kKC = 16;              // k per LDS chunk
 
-// One MFMA k-step group covers 16 consecutive k.  Lane (r = l%16, g = l/16)
-// supplies k = k0 + 4g + s at step s (s = 0..3): the four k of one lane are
-// contiguous in a row-major operand, and any fixed permutation of k used by
-// both operands leaves the product unchanged.
+// LDS row stride (elements): 16-byte aligned rows whose 16-byte fragment
+// reads by 16 consecutive rows fall on distinct banks.
+template <typename T> struct Lds { static constexpr int ld = sizeof(T) == 4 ? kKC + 4 : kKC + 2; };
+
+// Within a chunk, MFMA step s takes k = 4g + s from lane group g (g = l/16):
+// the four k of a lane are contiguous in an LDS row, read as one fragment.
+// For X . U the B operand is U's accumulator, whose lane group g holds rows
+// row(g, s); X is therefore stored with k at position pos(k) such that
+// position 4g + s holds k = row(g, s) (the identity for f32).
 template <typename T>
-struct Frag {
-    T v[4];
-};
+__device__ inline int xu_pos(int kk) { return Mfma<T>::row(1, 0) == 4 ? kk : 4 * (kk & 3) + (kk >> 2); }
 
-// A fragment: rows row0..row0+15 of a (rows x K) operand, k0..k0+15.
-// PAT 0: lane group g holds k = k0 + 4g + s; PAT 1: k = k0 + g + 4s.
-template <typename T, int PAT = 0>
-__device__ inline Frag<T> load_a(const T* __restrict__ p, int ld, bool tr, int row, int rows, int k0,
-                                 int K, int g, T scale) {
-    Frag<T> f;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int k = PAT == 0 ? k0 + 4 * g + s : k0 + g + 4 * s;
-        T x = 0;
-        if (row < rows && k < K) x = tr ? p[(int64_t)k * ld + row] : p[(int64_t)row * ld + k];
-        f.v[s] = scale * x;
+template <typename T>
+__device__ inline void lds_read4(const T* p, T (&f)[4]) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        f[0] = a.x; f[1] = a.y; f[2] = b.x; f[3] = b.y;
     }
-    return f;
 }
 
-// B fragment: column col of a (K x cols) operand, k0..k0+15
+__device__ inline bool is_identity(int flags) { return (flags & (F_ID_A | F_ID_B)) != 0; }
+
+// Element (32-bit offset) of a uniform base pointer: the byte offset stays
+// 32-bit so the load takes the scalar-base + vector-offset form.
 template <typename T>
-__device__ inline Frag<T> load_b(const T* __restrict__ p, int ld, bool tr, int col, int cols, int k0,
-                                 int K, int g) {
-    Frag<T> f;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int k = k0 + 4 * g + s;
-        T x = 0;
-        if (col < cols && k < K) x = tr ? p[(int64_t)col * ld + k] : p[(int64_t)k * ld + col];
-        f.v[s] = x;
-    }
-    return f;
+__device__ inline T ld_at(const T* p, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off * (uint32_t)sizeof(T));
 }
 
-template <typename T, int MT>
-__global__ __launch_bounds__(256) void chain_kernel(const Task* __restrict__ tasks,
-                                                    const Group* __restrict__ groups,
-                                                    const Contrib* __restrict__ contribs,
-                                                    Bases<T> B) {
+// A chunk of a task's work, all through the same LDS pipeline:
+//   kind 0: A . B of contribution c over k0..k0+15,
+//   kind 2: identity contribution c (U += alpha * operand), U rows k0..k0+15,
+//   kind 1: X . U over U rows k0..k0+15 of group g;  g < 0: none.
+// Kinds 1 and 2 work on the first row tile of U and then rotate the tiles by
+// one (register indices stay compile-time constants): X . U chunks run in
+// order k0 = 0, 16, ..., and after the last chunk of an identity
+// contribution the rotation is completed to a full turn.
+enum { CH_AB = 0, CH_XU = 1, CH_ID = 2 };
+struct Chunk { int g, c, k0, kind; };
+
+__device__ inline Chunk first_chunk(const Group* __restrict__ groups, const Contrib* __restrict__ contribs,
+                                    int g, int g1) {
+    for (; g < g1; ++g) {
+        const Group gr = groups[g];
+        if (gr.c1 > gr.c0) return Chunk{g, gr.c0, 0, is_identity(contribs[gr.c0].flags) ? CH_ID : CH_AB};
+        if (gr.flags & G_HAS_X) return Chunk{g, 0, 0, CH_XU};
+    }
+    return Chunk{-1, 0, 0, 0};
+}
+
+__device__ inline Chunk next_chunk(const Group* __restrict__ groups, const Contrib* __restrict__ contribs,
+                                   Chunk ch, int g1) {
+    const Group gr = groups[ch.g];
+    if (ch.kind == CH_XU) {
+        if (ch.k0 + kKC < gr.mu) return Chunk{ch.g, 0, ch.k0 + kKC, CH_XU};
+    } else {
+        const int extent = ch.kind == CH_AB ? contribs[ch.c].k : gr.mu;
+        if (ch.k0 + kKC < extent) return Chunk{ch.g, ch.c, ch.k0 + kKC, ch.kind};
+        if (ch.c + 1 < gr.c1)
+            return Chunk{ch.g, ch.c + 1, 0, is_identity(contribs[ch.c + 1].flags) ? CH_ID : CH_AB};
+        if (gr.flags & G_HAS_X) return Chunk{ch.g, 0, 0, CH_XU};
+    }
+    return first_chunk(groups, contribs, ch.g + 1, g1);
+}
+
+// Element e of a 16-wide chunk slot.  kcontig: 16 consecutive threads take
+// 16 consecutive inner indices (kk) of one row; otherwise 16 consecutive
+// rows of one kk.  Rows of the slot are 16 * (number of row tiles).
+__device__ inline void chunk_elem(int e, bool kcontig, int& row, int& kk) {
+    if (kcontig) { row = e >> 4; kk = e & 15; }
+    else { row = ((e >> 8) << 4) | (e & 15); kk = (e >> 4) & 15; }
+}
+
+// Minimum waves per SIMD each instantiation is compiled for (caps registers
+// at 512 / waves).
+template <typename T, int NCT> struct Occ { static constexpr int waves = sizeof(T) == 4 ? 4 : 2; };
+
+// The buffer table is read through the kernel-argument segment so that an
+// index known only at run time becomes a scalar load rather than a select
+// over registers; the table is the kernel's first argument (offset 0).
+template <typename T>
+__device__ inline const T* base_ptr(int buf, int vec) {
+    typedef const __attribute__((address_space(4))) Bases<T>* KPtr;
+    const KPtr b = (KPtr)__builtin_amdgcn_kernarg_segment_ptr();
+    return b->p[buf] + (int64_t)vec * b->vstride[buf];
+}
+
+template <typename T, int NCT>
+__global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Bases<T> Bargs,
+                                                                               const Task* __restrict__ tasks,
+                                                                               const Group* __restrict__ groups,
+                                                                               const Contrib* __restrict__ contribs) {
     using V4 = typename Mfma<T>::v4;
-    constexpr int RC = 64 * MT;
-    __shared__ T sU[RC * LDU_S];
+    constexpr int NT = 64 * NCT;
+    constexpr int LD = Lds<T>::ld;
+    constexpr int AR = 16 * kRT;                  // rows of the A / X slot
+    constexpr int BR = 16 * NCT;                  // rows (tile columns) of the B slot
+    constexpr int EA = (AR * kKC + NT - 1) / NT;  // A-slot elements per thread
+    constexpr int EB = BR * kKC / NT;             // B-slot elements per thread (4)
+    __shared__ __attribute__((aligned(16))) T sA[2][AR * LD];
+    __shared__ __attribute__((aligned(16))) T sB[2][BR * LD];
+    (void)Bargs;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int w = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
     const Task tk = tasks[blockIdx.x];
     const int vec = blockIdx.y;
+    const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
+    const int nrm = (tk.m + 15) >> 4;                // output row tiles
+    const int mycol = 16 * w + lr;                   // tile-local column of this lane
 
-    V4 acc[MT][2];
+    V4 acc[kRT], U[kRT];
 #pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
+    for (int i = 0; i < kRT; ++i) acc[i] = U[i] = V4{0, 0, 0, 0};
+    T ra[EA], rb[EB];
+    bool a_tr = false, b_tr = false;   // layout of the chunk held in ra / rb
+    int a_rows = 0;
 
-    for (int g = tk.g0; g < tk.g1; ++g) {
-        const Group gr = groups[g];
-        const int mu = gr.mu;
-        V4 U[MT][2];
+    // global -> registers: the operands of chunk ch
+    auto load = [&](const Chunk& ch) {
+        const Group gr = groups[ch.g];
+        if (ch.kind == CH_XU) {
+            const T* p = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
+            const int ld = gr.ldx, rows = tk.m, K = gr.mu;
+            const bool tr = (gr.flags & G_TRANS_X) != 0;
+            const T scale = (T)gr.x_coef;
+            const int nel = nrm * 256;
 #pragma unroll
-        for (int i = 0; i < MT; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) U[i][j] = V4{0, 0, 0, 0};
-
-        for (int c = gr.c0; c < gr.c1; ++c) {
-            const Contrib ct = contribs[c];
-            const int abuf = ct.flags & 7, bbuf = (ct.flags >> 3) & 7;
-            const T* Ap = B.p[abuf] + ct.a_off + (int64_t)vec * B.vstride[abuf];
-            const T* Bp = B.p[bbuf] + ct.b_off + (int64_t)vec * B.vstride[bbuf];
-            const T alpha = (T)ct.alpha;
+            for (int i = 0; i < EA; ++i) {
+                const int e = tid + i * NT;
+                int row, kk;
+                chunk_elem(e, !tr, row, kk);
+                const int k = ch.k0 + kk;
+                const uint32_t off = tr ? (uint32_t)(k * ld + row) : (uint32_t)(row * ld + k);
+                ra[i] = (e < nel && row < rows && k < K) ? scale * ld_at(p, off) : T(0);
+            }
+            a_tr = tr;
+            a_rows = rows;
+            return;
+        }
+        const Contrib ct = contribs[ch.c];
+        const T alpha = (T)ct.alpha;
+        if (ch.kind == CH_AB) {
+            const T* p = base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
+            const T* q = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
-            if (ct.flags & (F_ID_A | F_ID_B)) {
-                const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
+            const int lda = ct.lda, ldb = ct.ldb, rows = gr.mu, K = ct.k;
+            const int nel = ((rows + 15) >> 4) * 256;
 #pragma unroll
-                for (int i = 0; i < MT; ++i) {
-                    const int rt = wave + 4 * i;
-                    if (16 * rt >= mu) continue;
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const int col = tk.col0 + 16 * j + lr;
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = 16 * rt + Mfma<T>::row(lk, v);
-                            T val = 0;
-                            if (row < mu && col < tk.n) {
-                                if (ida && idb)   // a_off: diagonal offset of the identity
-                                    val = (row + ct.a_off == col) ? alpha : T(0);
-                                else if (ida)
-                                    val = alpha * (tb ? Bp[(int64_t)col * ct.ldb + row]
-                                                      : Bp[(int64_t)row * ct.ldb + col]);
-                                else
-                                    val = alpha * (ta ? Ap[(int64_t)col * ct.lda + row]
-                                                      : Ap[(int64_t)row * ct.lda + col]);
-                            }
-                            U[i][j][v] += val;
-                        }
-                    }
-                }
-                continue;
-            }
-            // U += alpha A . B, operands straight from global memory with the
-            // next 16-k chunk prefetched while the current one is multiplied
-            const int K = ct.k;
-            const int n = tk.n, c0 = tk.col0;
-            Frag<T> fa[MT], fb[2], na[MT], nb[2];
-#pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                const int rt = wave + 4 * i;
-                if (16 * rt < mu) fa[i] = load_a(Ap, ct.lda, ta, 16 * rt + lr, mu, 0, K, lk, alpha);
+            for (int i = 0; i < EA; ++i) {
+                const int e = tid + i * NT;
+                int row, kk;
+                chunk_elem(e, !ta, row, kk);
+                const int k = ch.k0 + kk;
+                const uint32_t off = ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k);
+                ra[i] = (e < nel && row < rows && k < K) ? alpha * ld_at(p, off) : T(0);
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) fb[j] = load_b(Bp, ct.ldb, tb, c0 + 16 * j + lr, n, 0, K, lk);
-            for (int k0 = 0; k0 < K; k0 += 16) {
-                const int k1 = k0 + 16;
-                if (k1 < K) {
+            for (int i = 0; i < EB; ++i) {
+                int col, kk;
+                chunk_elem(tid + i * NT, tb, col, kk);
+                const int k = ch.k0 + kk;
+                const int c = tk.col0 + col;
+                const uint32_t off = tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c);
+                rb[i] = (col < ncv && k < K) ? ld_at(q, off) : T(0);
+            }
+            a_tr = ta;
+            a_rows = rows;
+            b_tr = tb;
+            return;
+        }
+        // identity contribution: rows k0..k0+15 of alpha * operand (or of
+        // alpha * I shifted by a_off) into the B slot as [column][row]
+        const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
+        const T* p = ida ? base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off
+                         : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
+        const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
+        const int ld = ida ? ct.ldb : ct.lda;
 #pragma unroll
-                    for (int i = 0; i < MT; ++i) {
-                        const int rt = wave + 4 * i;
-                        if (16 * rt < mu) na[i] = load_a(Ap, ct.lda, ta, 16 * rt + lr, mu, k1, K, lk, alpha);
-                    }
+        for (int i = 0; i < EB; ++i) {
+            int col, kk;
+            chunk_elem(tid + i * NT, tp, col, kk);
+            const int row = ch.k0 + kk;
+            const int c = tk.col0 + col;
+            T x = 0;
+            if (col < ncv && row < gr.mu) {
+                if (ida && idb)   // a_off: diagonal offset of the identity
+                    x = ((int64_t)row + ct.a_off == c) ? alpha : T(0);
+                else
+                    x = alpha * ld_at(p, tp ? (uint32_t)(c * ld + row) : (uint32_t)(row * ld + c));
+            }
+            rb[i] = x;
+        }
+        b_tr = tp;
+    };
+    // registers -> LDS buffer b
+    auto store = [&](const Chunk& ch, int b) {
+        if (ch.kind != CH_XU) {
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) nb[j] = load_b(Bp, ct.ldb, tb, c0 + 16 * j + lr, n, k1, K, lk);
-                }
+            for (int i = 0; i < EB; ++i) {
+                int col, kk;
+                chunk_elem(tid + i * NT, b_tr, col, kk);
+                sB[b][col * LD + (ch.kind == CH_ID ? xu_pos<T>(kk) : kk)] = rb[i];
+            }
+        }
+        if (ch.kind != CH_ID) {
+            const int nel = ((a_rows + 15) >> 4) * 256;
 #pragma unroll
-                for (int i = 0; i < MT; ++i) {
-                    const int rt = wave + 4 * i;
-                    if (16 * rt >= mu) continue;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        U[i][0] = Mfma<T>::mma(fa[i].v[s], fb[0].v[s], U[i][0]);
-                        U[i][1] = Mfma<T>::mma(fa[i].v[s], fb[1].v[s], U[i][1]);
-                    }
-                }
-                if (k1 < K) {
-#pragma unroll
-                    for (int i = 0; i < MT; ++i) fa[i] = na[i];
-                    fb[0] = nb[0];
-                    fb[1] = nb[1];
+            for (int i = 0; i < EA; ++i) {
+                const int e = tid + i * NT;
+                if (e < nel) {
+                    int row, kk;
+                    chunk_elem(e, !a_tr, row, kk);
+                    sA[b][row * LD + (ch.kind == CH_XU ? xu_pos<T>(kk) : kk)] = ra[i];
                 }
             }
         }
+    };
 
-        if (gr.flags & G_HAS_X) {
-            // U is shared by all output rows: park it in LDS
-            __syncthreads();
+    Chunk cur = first_chunk(groups, contribs, tk.g0, tk.g1);
+    if (cur.g >= 0) load(cur);
+    int buf = 0, gcur = -1;
+    bool xid_pending = false;   // identity-X part of group gcur not yet added
+    auto add_xid = [&](int g) {
+        const T xi = (T)groups[g].xid_coef;
+        if (xi != T(0)) {
 #pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                const int rt = wave + 4 * i;
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        sU[(16 * rt + Mfma<T>::row(lk, v)) * LDU_S + 16 * j + lr] = U[i][j][v];
-            }
-            __syncthreads();
-            const int xbuf = gr.flags & 7;
-            const bool tx = (gr.flags & G_TRANS_X) != 0;
-            const T* Xp = B.p[xbuf] + gr.x_off + (int64_t)vec * B.vstride[xbuf];
-            const T xc = (T)gr.x_coef;
-            const int m = tk.m;
-            Frag<T> fx[MT], nx[MT];
-#pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                const int rt = wave + 4 * i;
-                if (16 * rt < m) fx[i] = load_a(Xp, gr.ldx, tx, 16 * rt + lr, m, 0, mu, lk, xc);
-            }
-            for (int k0 = 0; k0 < mu; k0 += 16) {
-                const int k1 = k0 + 16;
-                if (k1 < mu) {
-#pragma unroll
-                    for (int i = 0; i < MT; ++i) {
-                        const int rt = wave + 4 * i;
-                        if (16 * rt < m) nx[i] = load_a(Xp, gr.ldx, tx, 16 * rt + lr, m, k1, mu, lk, xc);
-                    }
-                }
-                T b0[4], b1[4];
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    // rows of U at or beyond mu are zero in LDS (their U tiles were zero)
-                    const int kr = k0 + 4 * lk + s;
-                    b0[s] = sU[kr * LDU_S + lr];
-                    b1[s] = sU[kr * LDU_S + 16 + lr];
-                }
-#pragma unroll
-                for (int i = 0; i < MT; ++i) {
-                    const int rt = wave + 4 * i;
-                    if (16 * rt >= m) continue;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        acc[i][0] = Mfma<T>::mma(fx[i].v[s], b0[s], acc[i][0]);
-                        acc[i][1] = Mfma<T>::mma(fx[i].v[s], b1[s], acc[i][1]);
-                    }
-                }
-                if (k1 < mu) {
-#pragma unroll
-                    for (int i = 0; i < MT; ++i) fx[i] = nx[i];
-                }
-            }
+            for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
         }
-        if (gr.xid_coef != 0.0) {
-            const T xi = (T)gr.xid_coef;
+    };
+    auto rotate_u = [&]() {
+        const V4 t = U[0];
 #pragma unroll
-            for (int i = 0; i < MT; ++i)
+        for (int i = 0; i < kRT - 1; ++i) U[i] = U[i + 1];
+        U[kRT - 1] = t;
+    };
+    while (cur.g >= 0) {
+        store(cur, buf);
+        __syncthreads();   // chunk cur complete in LDS; the buffer written next is free
+        const Chunk nx = next_chunk(groups, contribs, cur, tk.g1);
+        if (nx.g >= 0) load(nx);   // in flight during the MFMAs below
+        if (cur.g != gcur) {
+            if (xid_pending) add_xid(gcur);
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] += xi * U[i][j];
+            for (int i = 0; i < kRT; ++i) U[i] = V4{0, 0, 0, 0};
+            gcur = cur.g;
+            xid_pending = true;
         }
+        const T* A = sA[buf];
+        const T* Bs = sB[buf];
+        if (cur.kind == CH_AB) {
+            const int nru = (groups[cur.g].mu + 15) >> 4;
+            T bf[4];
+            lds_read4(Bs + mycol * LD + 4 * lk, bf);
+#pragma unroll
+            for (int i = 0; i < kRT; ++i) {
+                if (i >= nru) continue;
+                T af[4];
+                lds_read4(A + (16 * i + lr) * LD + 4 * lk, af);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(af[s], bf[s], U[i]);
+            }
+        } else if (cur.kind == CH_XU) {
+            if (xid_pending) {   // U is complete at the first X . U chunk
+                add_xid(gcur);
+                xid_pending = false;
+            }
+#pragma unroll
+            for (int i = 0; i < kRT; ++i) {
+                if (i >= nrm) continue;
+                T xf[4];
+                lds_read4(A + (16 * i + lr) * LD + 4 * lk, xf);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[s], U[0][s], acc[i]);
+            }
+            rotate_u();
+        } else {
+            T f[4];
+            lds_read4(Bs + mycol * LD + 4 * lk, f);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) U[0][v] += f[v];
+            rotate_u();
+            if (nx.g != cur.g || nx.c != cur.c || nx.kind != CH_ID)   // last chunk of the contribution
+                for (int r = (groups[cur.g].mu + 15) >> 4; r < kRT; ++r) rotate_u();
+        }
+        buf ^= 1;
+        cur = nx;
     }
+    if (xid_pending) add_xid(gcur);
 
     const int cbuf = tk.cbuf & 15;
     const bool accum = (tk.cbuf >> 8) & 1;
-    const int cshift = ((tk.cbuf >> 9) & 1) ? tk.col0 : 0;   // partial tiles store columns from 0
-    T* Cp = B.p[cbuf] + tk.c_off - cshift + (int64_t)vec * B.vstride[cbuf];
+    const bool local = (tk.cbuf >> 9) & 1;   // partial slot: columns from 0
+    T* Cp = const_cast<T*>(base_ptr<T>(cbuf, vec)) + tk.c_off + (local ? 0 : tk.col0);
+    if (mycol < ncv) {
 #pragma unroll
-    for (int i = 0; i < MT; ++i) {
-        const int rt = wave + 4 * i;
-        if (16 * rt >= tk.m) continue;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = tk.col0 + 16 * j + lr;
-            if (col >= tk.n) continue;
+        for (int i = 0; i < kRT; ++i) {
+            if (i >= nrm) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = 16 * rt + Mfma<T>::row(lk, v);
+                const int row = 16 * i + Mfma<T>::row(lk, v);
                 if (row < tk.m) {
-                    T* d = Cp + (int64_t)row * tk.ldc + col;
-                    *d = accum ? *d + acc[i][j][v] : acc[i][j][v];
+                    T* d = Cp + (uint32_t)(row * tk.ldc + mycol);
+                    *d = accum ? *d + acc[i][v] : acc[i][v];
                 }
             }
         }
     }
 }
 
-// Wave-per-task variant for tiles of at most 16*RT rows: each wave owns a whole
-// output tile (RT row tiles x 2 column tiles) and a whole group intermediate
-// U, so no LDS and no barrier is needed.  The accumulator layout of U is used
-// directly as the B operand of X . U: MFMA step (t, v) takes from lane group g
-// the U row held in register v of row tile t, and X is loaded with the same k
-// order (f32: k = 16t + 4g + v, f64: k = 16t + 4v + g).
-template <typename T, int RT>
-__global__ __launch_bounds__(256) void chain_wave_kernel(const Task* __restrict__ tasks, int ntask,
-                                                         const Group* __restrict__ groups,
-                                                         const Contrib* __restrict__ contribs,
-                                                         Bases<T> B) {
+// ---------------------------------------------------------------------------
+// wave_kernel: tiles of at most 16*RT rows (and U rows) x 16*CT columns.  One
+// wave per task, four independent tasks per workgroup, no LDS and no
+// barrier: MFMA fragments come straight from global memory and the
+// intermediate U stays in the accumulator registers (used as the B operand
+// of X . U with X loaded in the matching k order).  The small register
+// footprint allows many waves per SIMD, which is what hides the latency of
+// the short, dependent products of small sector blocks.
+// ---------------------------------------------------------------------------
+template <typename T, int RT, int CT> struct WaveOcc {
+    static constexpr int waves = sizeof(T) == 4 ? (RT * CT == 1 ? 6 : 5) : (RT * CT <= 2 ? 4 : 3);
+};
+
+template <typename T, int RT, int CT>
+__global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(Bases<T> Bargs, const Task* __restrict__ tasks, int ntask,
+                                                   const Group* __restrict__ groups,
+                                                   const Contrib* __restrict__ contribs) {
     using V4 = typename Mfma<T>::v4;
-    constexpr int XPAT = Mfma<T>::row(1, 0) == 4 ? 0 : 1;   // f32: rows 4g+v; f64: rows 4v+g
-    const int lane = threadIdx.x & 63;
+    (void)Bargs;
     const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ti >= ntask) return;
+    const int lane = threadIdx.x & 63;
     const int lr = lane & 15;
     const int lk = lane >> 4;
     const Task tk = tasks[ti];
     const int vec = blockIdx.y;
+    const int ncv = min(tk.ncol, tk.n - tk.col0);
 
-    V4 acc[RT][2];
+    V4 acc[RT][CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
+        for (int j = 0; j < CT; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
     for (int g = tk.g0; g < tk.g1; ++g) {
         const Group gr = groups[g];
         const int mu = gr.mu;
-        V4 U[RT][2];
+        V4 U[RT][CT];
 #pragma unroll
         for (int i = 0; i < RT; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) U[i][j] = V4{0, 0, 0, 0};
-
+            for (int j = 0; j < CT; ++j) U[i][j] = V4{0, 0, 0, 0};
         for (int c = gr.c0; c < gr.c1; ++c) {
             const Contrib ct = contribs[c];
-            const int abuf = ct.flags & 7, bbuf = (ct.flags >> 3) & 7;
-            const T* Ap = B.p[abuf] + ct.a_off + (int64_t)vec * B.vstride[abuf];
-            const T* Bp = B.p[bbuf] + ct.b_off + (int64_t)vec * B.vstride[bbuf];
             const T alpha = (T)ct.alpha;
-            const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
-            if (ct.flags & (F_ID_A | F_ID_B)) {
+            if (is_identity(ct.flags)) {
                 const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
+                const T* P = ida ? base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off
+                                 : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
+                const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
+                const int ld = ida ? ct.ldb : ct.lda;
 #pragma unroll
-                for (int i = 0; i < RT; ++i) {
-                    if (16 * i >= mu) continue;
+                for (int i = 0; i < RT; ++i)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const int col = tk.col0 + 16 * j + lr;
+                    for (int j = 0; j < CT; ++j) {
+                        const int col = 16 * j + lr;
+                        const int gc = tk.col0 + col;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int row = 16 * i + Mfma<T>::row(lk, v);
-                            T val = 0;
-                            if (row < mu && col < tk.n) {
+                            T x = 0;
+                            if (row < mu && col < ncv) {
                                 if (ida && idb)
-                                    val = (row + ct.a_off == col) ? alpha : T(0);
-                                else if (ida)
-                                    val = alpha * (tb ? Bp[(int64_t)col * ct.ldb + row]
-                                                      : Bp[(int64_t)row * ct.ldb + col]);
+                                    x = ((int64_t)row + ct.a_off == gc) ? alpha : T(0);
                                 else
-                                    val = alpha * (ta ? Ap[(int64_t)col * ct.lda + row]
-                                                      : Ap[(int64_t)row * ct.lda + col]);
+                                    x = alpha * ld_at(P, tp ? (uint32_t)(gc * ld + row) : (uint32_t)(row * ld + gc));
                             }
-                            U[i][j][v] += val;
+                            U[i][j][v] += x;
                         }
                     }
-                }
                 continue;
             }
-            const int K = ct.k;
-            const int n = tk.n, c0 = tk.col0;
-            const int nrt = (mu + 15) >> 4;
+            const T* Ap = base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
+            const T* Bp = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
+            const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
+            const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
             for (int k0 = 0; k0 < K; k0 += 16) {
-                Frag<T> fb0 = load_b(Bp, ct.ldb, tb, c0 + lr, n, k0, K, lk);
-                Frag<T> fb1 = load_b(Bp, ct.ldb, tb, c0 + 16 + lr, n, k0, K, lk);
-                Frag<T> fa[RT];
+                T fa[RT][4], fb[CT][4];
 #pragma unroll
-                for (int i = 0; i < RT; ++i)
-                    if (i < nrt) fa[i] = load_a(Ap, ct.lda, ta, 16 * i + lr, mu, k0, K, lk, alpha);
+                for (int s = 0; s < 4; ++s) {
+                    const int k = k0 + 4 * lk + s;
 #pragma unroll
-                for (int i = 0; i < RT; ++i) {
-                    if (i >= nrt) continue;
+                    for (int i = 0; i < RT; ++i) {
+                        const int row = 16 * i + lr;
+                        fa[i][s] = (row < mu && k < K)
+                                       ? alpha * ld_at(Ap, ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k))
+                                       : T(0);
+                    }
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        U[i][0] = Mfma<T>::mma(fa[i].v[s], fb0.v[s], U[i][0]);
-                        U[i][1] = Mfma<T>::mma(fa[i].v[s], fb1.v[s], U[i][1]);
+                    for (int j = 0; j < CT; ++j) {
+                        const int col = 16 * j + lr;
+                        const int gc = tk.col0 + col;
+                        fb[j][s] = (col < ncv && k < K)
+                                       ? ld_at(Bp, tb ? (uint32_t)(gc * ldb + k) : (uint32_t)(k * ldb + gc))
+                                       : T(0);
                     }
                 }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int i = 0; i < RT; ++i)
+#pragma unroll
+                        for (int j = 0; j < CT; ++j) U[i][j] = Mfma<T>::mma(fa[i][s], fb[j][s], U[i][j]);
             }
         }
-
         if (gr.flags & G_HAS_X) {
-            const int xbuf = gr.flags & 7;
+            const T* Xp = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
             const bool tx = (gr.flags & G_TRANS_X) != 0;
-            const T* Xp = B.p[xbuf] + gr.x_off + (int64_t)vec * B.vstride[xbuf];
             const T xc = (T)gr.x_coef;
-            const int m = tk.m;
-            const int nmt = (m + 15) >> 4;
+            const int ldx = gr.ldx;
 #pragma unroll
-            for (int t = 0; t < RT; ++t) {
-                if (16 * t >= mu) continue;
-                Frag<T> fx[RT];
+            for (int q = 0; q < RT; ++q) {      // U row tile = k tile of X . U
+                T xf[RT][4];
 #pragma unroll
-                for (int i = 0; i < RT; ++i)
-                    if (i < nmt) fx[i] = load_a<T, XPAT>(Xp, gr.ldx, tx, 16 * i + lr, m, 16 * t, mu, lk, xc);
+                for (int s = 0; s < 4; ++s) {
+                    const int k = 16 * q + Mfma<T>::row(lk, s);
 #pragma unroll
-                for (int i = 0; i < RT; ++i) {
-                    if (i >= nmt) continue;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        acc[i][0] = Mfma<T>::mma(fx[i].v[v], U[t][0][v], acc[i][0]);
-                        acc[i][1] = Mfma<T>::mma(fx[i].v[v], U[t][1][v], acc[i][1]);
+                    for (int i = 0; i < RT; ++i) {
+                        const int row = 16 * i + lr;
+                        xf[i][s] = (row < tk.m && k < mu)
+                                       ? xc * ld_at(Xp, tx ? (uint32_t)(k * ldx + row) : (uint32_t)(row * ldx + k))
+                                       : T(0);
                     }
                 }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int i = 0; i < RT; ++i)
+#pragma unroll
+                        for (int j = 0; j < CT; ++j) acc[i][j] = Mfma<T>::mma(xf[i][s], U[q][j][s], acc[i][j]);
             }
         }
         if (gr.xid_coef != 0.0) {
@@ -399,75 +493,80 @@ __global__ __launch_bounds__(256) void chain_wave_kernel(const Task* __restrict_
 #pragma unroll
             for (int i = 0; i < RT; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[i][j] += xi * U[i][j];
+                for (int j = 0; j < CT; ++j) acc[i][j] += xi * U[i][j];
         }
     }
 
     const int cbuf = tk.cbuf & 15;
     const bool accum = (tk.cbuf >> 8) & 1;
-    const int cshift = ((tk.cbuf >> 9) & 1) ? tk.col0 : 0;   // partial tiles store columns from 0
-    T* Cp = B.p[cbuf] + tk.c_off - cshift + (int64_t)vec * B.vstride[cbuf];
+    const bool local = (tk.cbuf >> 9) & 1;
+    T* Cp = const_cast<T*>(base_ptr<T>(cbuf, vec)) + tk.c_off + (local ? 0 : tk.col0);
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        if (16 * i >= tk.m) continue;
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = tk.col0 + 16 * j + lr;
-            if (col >= tk.n) continue;
+        for (int j = 0; j < CT; ++j) {
+            const int col = 16 * j + lr;
+            if (col >= ncv) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * i + Mfma<T>::row(lk, v);
                 if (row < tk.m) {
-                    T* d = Cp + (int64_t)row * tk.ldc + col;
+                    T* d = Cp + (uint32_t)(row * tk.ldc + col);
                     *d = accum ? *d + acc[i][j][v] : acc[i][j][v];
                 }
             }
         }
-    }
 }
 
 template <typename T>
-static int launch_chain(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
-                        const Bases<T>& b, int nvec, void* stream) {
+static int launch_chain(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
+                        int nvec, void* stream) {
     if (ntask <= 0) return 0;
-    dim3 grid(ntask, nvec), block(256);
     hipStream_t s = (hipStream_t)stream;
-    dim3 wgrid((ntask + 3) / 4, nvec);
-    if (variant == 1 && cls == 0)
-        hipLaunchKernelGGL((chain_wave_kernel<T, 4>), wgrid, block, 0, s, t, ntask, g, c, b);
-    else if (variant == 1 && cls == 1)
-        hipLaunchKernelGGL((chain_wave_kernel<T, 8>), wgrid, block, 0, s, t, ntask, g, c, b);
-    else if (cls == 0)
-        hipLaunchKernelGGL((chain_kernel<T, 1>), grid, block, 0, s, t, g, c, b);
-    else if (cls == 1)
-        hipLaunchKernelGGL((chain_kernel<T, 2>), grid, block, 0, s, t, g, c, b);
-    else
-        hipLaunchKernelGGL((chain_kernel<T, 5>), grid, block, 0, s, t, g, c, b);
+    if (cls >= kNumTileClass) {   // wave classes: four tasks per workgroup
+        const dim3 grid((ntask + 3) / 4, nvec), block(256);
+        switch (cls - kNumTileClass) {
+            case 0: hipLaunchKernelGGL((wave_kernel<T, 1, 1>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 1: hipLaunchKernelGGL((wave_kernel<T, 1, 2>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 2: hipLaunchKernelGGL((wave_kernel<T, 2, 1>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 3: hipLaunchKernelGGL((wave_kernel<T, 2, 2>), grid, block, 0, s, b, t, ntask, g, c); break;
+            default: return (int)hipErrorInvalidValue;
+        }
+        return (int)hipGetLastError();
+    }
+    const dim3 grid(ntask, nvec), block(64 * (cls + 1));
+    switch (cls) {
+        case 0: hipLaunchKernelGGL((tile_kernel<T, 1>), grid, block, 0, s, b, t, g, c); break;
+        case 1: hipLaunchKernelGGL((tile_kernel<T, 2>), grid, block, 0, s, b, t, g, c); break;
+        case 2: hipLaunchKernelGGL((tile_kernel<T, 3>), grid, block, 0, s, b, t, g, c); break;
+        case 3: hipLaunchKernelGGL((tile_kernel<T, 4>), grid, block, 0, s, b, t, g, c); break;
+        case 4: hipLaunchKernelGGL((tile_kernel<T, 5>), grid, block, 0, s, b, t, g, c); break;
+        case 5: hipLaunchKernelGGL((tile_kernel<T, 6>), grid, block, 0, s, b, t, g, c); break;
+        default: return (int)hipErrorInvalidValue;
+    }
     return (int)hipGetLastError();
 }
 
-int launch_chain_f64(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f64(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<double>& b, int nvec, void* stream) {
-    return launch_chain<double>(cls, variant, t, ntask, g, c, b, nvec, stream);
+    return launch_chain<double>(cls, t, ntask, g, c, b, nvec, stream);
 }
-int launch_chain_f32(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f32(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<float>& b, int nvec, void* stream) {
-    return launch_chain<float>(cls, variant, t, ntask, g, c, b, nvec, stream);
+    return launch_chain<float>(cls, t, ntask, g, c, b, nvec, stream);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_kernel(const Reduce* __restrict__ red, Bases<T> b) {
     const Reduce r = red[blockIdx.x];
     const int vec = blockIdx.y;
-    const int ncol = min(32, r.n - r.col0);
     const int cbuf = r.cbuf & 15;
     const bool accum = (r.cbuf >> 8) & 1;
     const T* P = b.p[kPartialBuf] + r.poff + (int64_t)vec * b.vstride[kPartialBuf];
     T* Cp = b.p[cbuf] + r.c_off + (int64_t)vec * b.vstride[cbuf];
-    const int64_t slot = (int64_t)r.m * 32;
-    for (int e = threadIdx.x; e < r.m * 32; e += blockDim.x) {
-        const int row = e >> 5, j = e & 31;
-        if (j >= ncol) continue;
+    const int64_t slot = (int64_t)r.m * r.ncol;
+    for (int e = threadIdx.x; e < slot; e += blockDim.x) {
+        const int row = e / r.ncol, j = e - row * r.ncol;
         T s = 0;
         for (int q = 0; q < r.nslot; ++q) s += P[q * slot + e];
         T* d = Cp + (int64_t)row * r.ldc + r.col0 + j;

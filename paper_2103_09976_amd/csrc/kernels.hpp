@@ -2,17 +2,17 @@
 //
 // Everything heavy (blocking + transformation, the normal->complementary
 // transform, the integral-weighted operator sums and H_eff psi) is expressed
-// as one kind of work: an output tile C (rows x 32 columns of a sector
-// block) accumulated as
+// as one kind of work: an output tile C (up to 96 rows x 96 columns of a
+// sector block) accumulated as
 //
 //     C = sum_groups [ x_coef * X_g . U_g + xid_coef * U_g ],
 //     U_g = sum_{c in g} alpha_c * A_c . B_c
 //
-// where every operand is a dense sector block in one of up to eight device
+// where every operand is a dense sector block in one of eight device
 // buffers, optionally transposed or an identity.  For H_eff psi, A_c is a
 // psi sub-block, B_c a right operator block (transposed) and X_g a left
 // operator block: the two products of one term run back to back with the
-// intermediate U_g staged in LDS (never written to HBM).  For the
+// intermediate U_g held in registers (never written to memory).  For the
 // transformation U^T O U, X_g = U^T, A_c = O (each component of the
 // blocked operator), B_c = U.  A plain GEMM is the case X = identity with a
 // single contribution.  Tiles are owned by exactly one workgroup and
@@ -22,7 +22,8 @@
 
 namespace dmrgk {
 
-constexpr int kTN = 32;          // output columns per task
+constexpr int kMaxRows = 96;     // rows of an output tile, and of U (inner dimension of X . U)
+constexpr int kMaxCols = 96;     // columns of an output tile
 constexpr int kMaxBuf = 9;       // buffer 8: partial tiles of split tasks
 
 // flag bits
@@ -31,12 +32,13 @@ enum : int32_t {
     G_TRANS_X = 1 << 3, G_HAS_X = 1 << 4,
 };
 
-struct Task {          // one output tile
-    int64_t c_off;     // element offset of the block in buffer cbuf
-    int32_t ldc, m, n; // block rows, columns (tile covers columns col0..col0+31)
-    int32_t col0;
+struct Task {          // one output tile: rows 0..m-1, columns col0..col0+ncol-1 of a block
+    int64_t c_off;     // element offset of the block (of the partial slot, if tile-local) in buffer cbuf
+    int32_t ldc, m, n; // row stride, rows, columns of the whole block
+    int32_t col0, ncol;
     int32_t g0, g1;    // group range
     int32_t cbuf;      // buffer id of C (bits 0-3) | accumulate << 8 | tile-local columns << 9
+    int32_t pad;
 };
 
 struct Group {
@@ -61,28 +63,35 @@ struct Bases {
     int64_t vstride[kMaxBuf];   // per-vector stride (batched vectors, grid.y)
 };
 
-// row classes: tasks whose rows (and U rows) fit 64, 128 or 320
-constexpr int kNumClass = 3;
-constexpr int kClassRows[kNumClass] = {64, 128, 320};
-
-// Kernel variants per row class: 0 = four waves cooperate on one tile (U shared
-// through LDS), 1 = one wave per tile (U in registers; classes 0 and 1 only).
-constexpr int kNumVariant = 2;
+// Task classes.  Tile classes c < kNumTileClass: tiles of 16c+1 .. 16c+16
+// columns, run by c+1 waves (one per 16-column slice) with LDS staging.
+// Wave classes kNumTileClass + (RT-1)*2 + (CT-1): tiles whose rows and U
+// rows fit 16*RT and whose columns fit 16*CT (RT, CT <= 2), one wave each.
+constexpr int kNumTileClass = kMaxCols / 16;
+constexpr int kNumClass = kNumTileClass + 4;
+inline int col_class(int ncol) { return (ncol + 15) / 16 - 1; }
+// rows: max of the tile rows and of every group's mu
+inline int task_class(int rows, int ncol) {
+    if (rows <= 32 && ncol <= 32) return kNumTileClass + ((rows + 15) / 16 - 1) * 2 + (ncol + 15) / 16 - 1;
+    return col_class(ncol);
+}
+inline int class_rows(int cls) { return cls < kNumTileClass ? kMaxRows : 16 * ((cls - kNumTileClass) / 2 + 1); }
+inline int class_cols(int cls) { return cls < kNumTileClass ? 16 * (cls + 1) : 16 * ((cls - kNumTileClass) % 2 + 1); }
 
 // launchers (return hipError_t as int)
-int launch_chain_f64(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f64(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<double>& b, int nvec, void* stream);
-int launch_chain_f32(int cls, int variant, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f32(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<float>& b, int nvec, void* stream);
 
 // A task whose group range is split writes each chunk's tile to its own slot
-// of the partial buffer (tile-local: ldc = 32, columns from 0); the slots are
-// then summed in slot order, so the result does not depend on scheduling:
-//   C[r][col0 + j] (+)= sum_{s < nslot} P[poff + s*m*32 + r*32 + j]
+// of the partial buffer (tile-local: m x ncol, row stride ncol); the slots
+// are then summed in slot order, so the result does not depend on scheduling:
+//   C[r][col0 + j] (+)= sum_{s < nslot} P[poff + s*m*ncol + r*ncol + j]
 constexpr int kPartialBuf = 8;
 struct Reduce {
     int64_t c_off, poff;
-    int32_t ldc, m, n, col0, nslot;
+    int32_t ldc, m, col0, ncol, nslot;
     int32_t cbuf;      // buffer id of C | accumulate << 8
 };
 int launch_reduce_f64(const Reduce* r, int nred, const Bases<double>& b, int nvec, void* stream);

@@ -21,6 +21,7 @@ DMRG_LEFT, DMRG_RIGHT = 0, 1
 DMRG_SCHEME_NC, DMRG_SCHEME_CN = 0, 1
 DMRG_F64, DMRG_F32 = 0, 1
 DMRG_PREC_F64, DMRG_PREC_F32 = 0, 1
+DMRG_HEFF_LAUNCHES = 11   # kernel launches of one H_eff product (dmrg_heff_profile)
 
 SITE_Q = ((0, 0), (1, 0), (0, 1), (1, 1))
 
@@ -78,6 +79,9 @@ _SIGS = {
     "dmrg_heff_bytes": (C.c_int64, [C.c_void_p, C.c_int32]),
     "dmrg_heff_terms": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]),
+    "dmrg_heff_profile": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                      C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                      C.c_void_p]),
     "dmrg_opset_basis": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "dmrg_opset_block": (C.c_int32, [C.c_void_p, C.c_char, C.c_int32, C.c_int32, C.c_void_p,
                                      C.c_void_p, C.c_int64]),
@@ -187,6 +191,21 @@ class Heff:
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
         load().dmrg_heff_terms(self.ptr, C.byref(a), C.byref(b), C.byref(c))
         return a.value, b.value, c.value
+
+    def profile(self, psi, sigma, precision: int = DMRG_PREC_F64):
+        """One product with every kernel launch timed (HIP events on the current
+        stream): list of (kind, ms, useful_flops) per launch, in launch-slot order."""
+        import torch
+        want = torch.float64 if precision == DMRG_PREC_F64 else torch.float32
+        assert psi.dtype == want and sigma.dtype == want and psi.is_cuda and sigma.is_cuda
+        assert psi.numel() >= self.dim and sigma.numel() >= self.dim
+        n = DMRG_HEFF_LAUNCHES
+        ms, fl, kd = (C.c_float * n)(), (C.c_double * n)(), (C.c_int32 * n)()
+        r = load().dmrg_heff_profile(self.ptr, precision, C.c_void_p(psi.data_ptr()),
+                                     C.c_void_p(sigma.data_ptr()), n, ms, fl, kd, _stream(torch))
+        if r < 0:
+            _check(r)
+        return [(int(kd[i]), float(ms[i]), float(fl[i])) for i in range(r)]
 
     def apply(self, psi, sigma, precision: int = DMRG_PREC_F64, n_vec: int = 1):
         import torch

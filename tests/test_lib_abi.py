@@ -54,4 +54,11 @@ def test_null_arguments_are_rejected(lib):
     assert lib.dmrg_set_integrals(None, 8, 8, 0, None, None, 0.0, 1, 1) == -1
     assert lib.dmrg_heff_flops(None) == -1
     assert lib.dmrg_davidson(None, 1, None, None, None, None, None) == -1
+    assert lib.dmrg_heff_profile(None, 0, None, None, 0, None, None, None, None) == -1
     assert dmrg.DMRG_OK == 0
+
+
+def test_launch_count_matches_header():
+    from paper_2103_09976_amd import dmrg
+    m = re.search(r"#define\s+DMRG_HEFF_LAUNCHES\s+(\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == dmrg.DMRG_HEFF_LAUNCHES
