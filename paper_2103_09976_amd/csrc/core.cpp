@@ -533,12 +533,23 @@ double task_cost(const WorkList& w, const dmrgk::Task& t) {
     return f;
 }
 
+bool records_fit(const WorkList& w, const dmrgk::Task& t) {
+    if (t.g1 - t.g0 > dmrgk::kRecG) return false;
+    if (t.g1 <= t.g0) return true;
+    for (int g = t.g0 + 1; g < t.g1; ++g)
+        if (w.groups[g].c0 != w.groups[g - 1].c1) return false;
+    return w.groups[t.g1 - 1].c1 - w.groups[t.g0].c0 <= dmrgk::kRecC;
+}
+
 void balance_work(WorkList& w, int target_tasks) {
     double total = 0;
     for (auto& T : w.task)
         for (const dmrgk::Task& t : T) total += task_cost(w, t);
     if (total <= 0 || target_tasks < 1) return;
-    const double cap = total / target_tasks;
+    // chunks of at least kMinChunkCost: small problems are not cut into pieces
+    // whose fixed cost (records, partial tile, reduction) exceeds their work
+    const double kMinChunkCost = 4.0e6;
+    const double cap = std::max(total / target_tasks, kMinChunkCost);
     std::vector<std::pair<double, dmrgk::Task>> out[dmrgk::kNumClass];
     int64_t poff = w.partial_elems;
     std::vector<double> gc;
@@ -548,12 +559,13 @@ void balance_work(WorkList& w, int target_tasks) {
             double tc = 0;
             for (int g = t.g0; g < t.g1; ++g) tc += gc[g - t.g0] = group_cost(w, w.groups[g], t.m, t.ncol);
             const int nchunk = (int)std::min<double>(std::ceil(tc / cap), t.g1 - t.g0);
-            if (nchunk <= 1) {
+            if (nchunk <= 1 && records_fit(w, t)) {
                 out[task_class_of(w, t)].emplace_back(tc, t);
                 continue;
             }
-            // greedy cut at multiples of tc / nchunk
-            const double per = tc / nchunk;
+            // greedy cut at multiples of tc / nchunk, and wherever the next group would
+            // overflow the records a task can stage (kRecG groups, kRecC contributions)
+            const double per = tc / std::max(1, nchunk);
             int slot = 0;
             int a = t.g0;
             double run = 0, done = 0;
@@ -561,7 +573,13 @@ void balance_work(WorkList& w, int target_tasks) {
             for (int g = t.g0; g < t.g1; ++g) {
                 run += gc[g - t.g0];
                 const bool last = g + 1 == t.g1;
-                if (!last && done + run < per * (slot + 1)) continue;
+                bool cut = last || done + run >= per * (slot + 1);
+                if (!cut) {
+                    const dmrgk::Group& N = w.groups[g + 1];
+                    cut = g + 2 - a > dmrgk::kRecG || N.c1 - w.groups[a].c0 > dmrgk::kRecC ||
+                          N.c0 != w.groups[g].c1;
+                }
+                if (!cut) continue;
                 dmrgk::Task u = t;
                 u.g0 = a;
                 u.g1 = g + 1;
@@ -711,6 +729,9 @@ dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
     if (!w.contribs.empty())
         DMRG_HIP(hipMemcpyAsync(d.contribs, w.contribs.data(), w.contribs.size() * sizeof(dmrgk::Contrib),
                                 hipMemcpyHostToDevice, s));
+    d.lds_records = true;
+    for (const auto& T : w.task)
+        for (const dmrgk::Task& t : T) d.lds_records = d.lds_records && records_fit(w, t);
     d.reduces = (dmrgk::Reduce*)(base + roff);
     d.nred = (int)w.reduces.size();
     if (!w.reduces.empty())
@@ -727,14 +748,16 @@ void free_work(Ctx* ctx, DevWork& d) {
 
 dmrg_status run_work_f64(const DevWork& d, const dmrgk::Bases<double>& b, int nvec, void* stream) {
     for (int c = dmrgk::kNumClass - 1; c >= 0; --c)
-        DMRG_HIP(dmrgk::launch_chain_f64(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec, stream));
+        DMRG_HIP(dmrgk::launch_chain_f64(c, d.lds_records, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec,
+                                         stream));
     DMRG_HIP(dmrgk::launch_reduce_f64(d.reduces, d.nred, b, nvec, stream));
     return DMRG_OK;
 }
 
 dmrg_status run_work_f32(const DevWork& d, const dmrgk::Bases<float>& b, int nvec, void* stream) {
     for (int c = dmrgk::kNumClass - 1; c >= 0; --c)
-        DMRG_HIP(dmrgk::launch_chain_f32(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec, stream));
+        DMRG_HIP(dmrgk::launch_chain_f32(c, d.lds_records, d.task[c], d.ntask[c], d.groups, d.contribs, b, nvec,
+                                         stream));
     DMRG_HIP(dmrgk::launch_reduce_f32(d.reduces, d.nred, b, nvec, stream));
     return DMRG_OK;
 }
@@ -747,7 +770,7 @@ static dmrg_status run_timed(const DevWork& d, const dmrgk::Bases<T>& b, float* 
     dmrg_status st = DMRG_OK;
     for (int c = dmrgk::kNumClass - 1; c >= 0 && st == DMRG_OK; --c) {   // classes high -> low, then reduce
         hipEventRecord(ev[2 * c], s);
-        const int e = chain(c, d.task[c], d.ntask[c], d.groups, d.contribs, b, 1, stream);
+        const int e = chain(c, d.lds_records, d.task[c], d.ntask[c], d.groups, d.contribs, b, 1, stream);
         hipEventRecord(ev[2 * c + 1], s);
         if (e) st = hip_fail(e, "kernel launch");
     }

@@ -228,6 +228,7 @@ struct DevWork {
     dmrgk::Contrib* contribs = nullptr;
     dmrgk::Reduce* reduces = nullptr;
     int nred = 0;
+    bool lds_records = false;               // every task's records fit the kernels' LDS staging
     double useful[dmrgk::kNumClass] = {};   // useful MFMA flops per class (one vector)
 };
 dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
@@ -240,6 +241,8 @@ void split_large(WorkList& w);
 // reduction sums in fixed order), then orders every class by decreasing cost.
 void balance_work(WorkList& w, int target_tasks);
 double task_cost(const WorkList& w, const dmrgk::Task& t);
+// the task's records fit the LDS staging (kRecG groups, kRecC contiguous contributions)
+bool records_fit(const WorkList& w, const dmrgk::Task& t);
 // class of a task: by its columns and the largest of its rows and group mu
 int task_class_of(const WorkList& w, const dmrgk::Task& t);
 void free_work(Ctx* ctx, DevWork& d);

@@ -1,7 +1,7 @@
 // HIP kernels (gfx950) of the DMRG library.
 //
 // tile_kernel: the grouped, output-stationary sector-GEMM engine described
-// in kernels.hpp.  A workgroup of NCT waves owns one output tile of up to 96
+// in kernels.hpp.  A workgroup of NCT waves owns one output tile of up to 80
 // rows x 16*NCT columns; wave w owns the 16-column slice w of both the tile
 // and every group intermediate U.  Per group, U (mu x 16 per wave) is
 // accumulated in MFMA registers over the contributions and then used
@@ -12,6 +12,7 @@
 // the MFMAs of the current one run.  MFMA 16x16x4 in f64 or f32.
 #include <hip/hip_runtime.h>
 #include <cmath>
+#include <type_traits>
 #include "kernels.hpp"
 
 namespace dmrgk {
@@ -65,6 +66,33 @@ __device__ inline void lds_read4(const T* p, T (&f)[4]) {
 
 __device__ inline bool is_identity(int flags) { return (flags & (F_ID_A | F_ID_B)) != 0; }
 
+// Calls f(std::integral_constant<int, j>) for a run-time j in [0, 6): one
+// case per value, opened and closed by distinct empty asm comments so that
+// the compiler can neither merge the cases nor hoist or sink their common
+// code into one block that indexes a register array with j (which it would
+// lower to selects or scratch memory).
+#define DMRG_TILE_CASE(n)                                  \
+    case n:                                                \
+        asm volatile("; tile " #n " begin");               \
+        f(std::integral_constant<int, n>{});               \
+        asm volatile("; tile " #n " end");                 \
+        break;
+template <typename F>
+__device__ __forceinline__ void tile_switch(int j, F&& f) {
+    switch (j) {
+        DMRG_TILE_CASE(0)
+        DMRG_TILE_CASE(1)
+        DMRG_TILE_CASE(2)
+        DMRG_TILE_CASE(3)
+        DMRG_TILE_CASE(4)
+#if DMRG_MAX_ROWS > 80
+        DMRG_TILE_CASE(5)
+#endif
+        default: break;
+    }
+}
+#undef DMRG_TILE_CASE
+
 // Element (32-bit offset) of a uniform base pointer: the byte offset stays
 // 32-bit so the load takes the scalar-base + vector-offset form.
 template <typename T>
@@ -76,36 +104,86 @@ __device__ inline T ld_at(const T* p, uint32_t off) {
 //   kind 0: A . B of contribution c over k0..k0+15,
 //   kind 2: identity contribution c (U += alpha * operand), U rows k0..k0+15,
 //   kind 1: X . U over U rows k0..k0+15 of group g;  g < 0: none.
-// Kinds 1 and 2 work on the first row tile of U and then rotate the tiles by
-// one (register indices stay compile-time constants): X . U chunks run in
-// order k0 = 0, 16, ..., and after the last chunk of an identity
-// contribution the rotation is completed to a full turn.
+// X . U chunks come last in their group.
 enum { CH_AB = 0, CH_XU = 1, CH_ID = 2 };
 struct Chunk { int g, c, k0, kind; };
 
-__device__ inline Chunk first_chunk(const Group* __restrict__ groups, const Contrib* __restrict__ contribs,
-                                    int g, int g1) {
+// Group / contribution records of a task.  LR = false: straight from global
+// memory (scalar loads).  LR = true: the task's records were copied to LDS
+// once at its start (one coalesced load), so the per-chunk descriptor reads
+// are LDS reads; values are made wave-uniform with readfirstlane.
+template <typename R>
+__device__ inline R lds_uniform(const R* p) {
+    static_assert(sizeof(R) % 4 == 0, "record size");
+    R r;
+    const int* s = reinterpret_cast<const int*>(p);
+    int* d = reinterpret_cast<int*>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(R) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(s[i]);
+    return r;
+}
+
+template <bool LR> struct Recs;
+template <> struct Recs<false> {
+    const Group* __restrict__ G;
+    const Contrib* __restrict__ C;
+    __device__ Group group(int g) const { return G[g]; }
+    __device__ Contrib contrib(int c) const { return C[c]; }
+    __device__ int cflags(int c) const { return C[c].flags; }
+    __device__ int ck(int c) const { return C[c].k; }
+    __device__ int gmu(int g) const { return G[g].mu; }
+};
+template <> struct Recs<true> {
+    const Group* sg;
+    const Contrib* sc;
+    int g0, cb;
+    __device__ Group group(int g) const { return lds_uniform(sg + (g - g0)); }
+    __device__ Contrib contrib(int c) const { return lds_uniform(sc + (c - cb)); }
+    __device__ int cflags(int c) const { return __builtin_amdgcn_readfirstlane(sc[c - cb].flags); }
+    __device__ int ck(int c) const { return __builtin_amdgcn_readfirstlane(sc[c - cb].k); }
+    __device__ int gmu(int g) const { return __builtin_amdgcn_readfirstlane(sg[g - g0].mu); }
+};
+
+// copies the records of groups g0..g1-1 and of their (contiguous)
+// contributions to LDS with threads tid = 0..nt-1; returns the first
+// contribution index
+__device__ inline int stage_records(const Group* __restrict__ groups, const Contrib* __restrict__ contribs, int g0,
+                                    int g1, Group* sg, Contrib* sc, int tid, int nt) {
+    if (g1 <= g0) return 0;
+    const int cb = groups[g0].c0;
+    const int nc = groups[g1 - 1].c1 - cb;
+    const int* gs = reinterpret_cast<const int*>(groups + g0);
+    int* gd = reinterpret_cast<int*>(sg);
+    for (int i = tid; i < (g1 - g0) * (int)(sizeof(Group) / 4); i += nt) gd[i] = gs[i];
+    const int* cs = reinterpret_cast<const int*>(contribs + cb);
+    int* cd = reinterpret_cast<int*>(sc);
+    for (int i = tid; i < nc * (int)(sizeof(Contrib) / 4); i += nt) cd[i] = cs[i];
+    return cb;
+}
+
+template <class RC>
+__device__ inline Chunk first_chunk(const RC& R, int g, int g1) {
     for (; g < g1; ++g) {
-        const Group gr = groups[g];
-        if (gr.c1 > gr.c0) return Chunk{g, gr.c0, 0, is_identity(contribs[gr.c0].flags) ? CH_ID : CH_AB};
+        const Group gr = R.group(g);
+        if (gr.c1 > gr.c0) return Chunk{g, gr.c0, 0, is_identity(R.cflags(gr.c0)) ? CH_ID : CH_AB};
         if (gr.flags & G_HAS_X) return Chunk{g, 0, 0, CH_XU};
     }
     return Chunk{-1, 0, 0, 0};
 }
 
-__device__ inline Chunk next_chunk(const Group* __restrict__ groups, const Contrib* __restrict__ contribs,
-                                   Chunk ch, int g1) {
-    const Group gr = groups[ch.g];
+template <class RC>
+__device__ inline Chunk next_chunk(const RC& R, Chunk ch, int g1) {
+    const Group gr = R.group(ch.g);
     if (ch.kind == CH_XU) {
         if (ch.k0 + kKC < gr.mu) return Chunk{ch.g, 0, ch.k0 + kKC, CH_XU};
     } else {
-        const int extent = ch.kind == CH_AB ? contribs[ch.c].k : gr.mu;
+        const int extent = ch.kind == CH_AB ? R.ck(ch.c) : gr.mu;
         if (ch.k0 + kKC < extent) return Chunk{ch.g, ch.c, ch.k0 + kKC, ch.kind};
         if (ch.c + 1 < gr.c1)
-            return Chunk{ch.g, ch.c + 1, 0, is_identity(contribs[ch.c + 1].flags) ? CH_ID : CH_AB};
+            return Chunk{ch.g, ch.c + 1, 0, is_identity(R.cflags(ch.c + 1)) ? CH_ID : CH_AB};
         if (gr.flags & G_HAS_X) return Chunk{ch.g, 0, 0, CH_XU};
     }
-    return first_chunk(groups, contribs, ch.g + 1, g1);
+    return first_chunk(R, ch.g + 1, g1);
 }
 
 // Element e of a 16-wide chunk slot.  kcontig: 16 consecutive threads take
@@ -116,9 +194,10 @@ __device__ inline void chunk_elem(int e, bool kcontig, int& row, int& kk) {
     else { row = ((e >> 8) << 4) | (e & 15); kk = (e >> 4) & 15; }
 }
 
-// Minimum waves per SIMD each instantiation is compiled for (caps registers
-// at 512 / waves).
-template <typename T, int NCT> struct Occ { static constexpr int waves = sizeof(T) == 4 ? 4 : 2; };
+// Minimum waves per SIMD each tile-kernel instantiation is compiled for
+// (caps registers at 512 / waves), chosen by measurement: FP32 tiles of three
+// or more slices fit 128 registers; narrower FP32 tiles and FP64 tiles need more.
+template <typename T, int NCT> struct Occ { static constexpr int waves = sizeof(T) == 4 ? (NCT <= 2 ? 3 : 4) : 2; };
 
 // The buffer table is read through the kernel-argument segment so that an
 // index known only at run time becomes a scalar load rather than a select
@@ -130,7 +209,7 @@ __device__ inline const T* base_ptr(int buf, int vec) {
     return b->p[buf] + (int64_t)vec * b->vstride[buf];
 }
 
-template <typename T, int NCT>
+template <typename T, int NCT, bool LR>
 __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Bases<T> Bargs,
                                                                                const Task* __restrict__ tasks,
                                                                                const Group* __restrict__ groups,
@@ -144,6 +223,8 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     constexpr int EB = BR * kKC / NT;             // B-slot elements per thread (4)
     __shared__ __attribute__((aligned(16))) T sA[2][AR * LD];
     __shared__ __attribute__((aligned(16))) T sB[2][BR * LD];
+    __shared__ Group sG[LR ? kRecG : 1];
+    __shared__ Contrib sC[LR ? kRecC : 1];
     (void)Bargs;
 
     const int tid = threadIdx.x;
@@ -156,62 +237,87 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
     const int nrm = (tk.m + 15) >> 4;                // output row tiles
     const int mycol = 16 * w + lr;                   // tile-local column of this lane
+    Recs<LR> R;
+    if constexpr (LR) {
+        const int cb = stage_records(groups, contribs, tk.g0, tk.g1, sG, sC, tid, NT);
+        __syncthreads();
+        R = Recs<true>{sG, sC, tk.g0, cb};
+    } else {
+        R = Recs<false>{groups, contribs};
+    }
 
     V4 acc[kRT], U[kRT];
 #pragma unroll
     for (int i = 0; i < kRT; ++i) acc[i] = U[i] = V4{0, 0, 0, 0};
+    // Operands of the next chunk in flight: every load is issued unconditionally
+    // (out-of-range elements read offset 0 of their block, which is always valid)
+    // and masked when written to LDS, so no wait is needed before the MFMAs of
+    // the current chunk.
     T ra[EA], rb[EB];
-    bool a_tr = false, b_tr = false;   // layout of the chunk held in ra / rb
+    uint32_t a_ok = 0, b_ok = 0;           // element i valid
+    T a_scale = 0, b_scale = 0;
+    bool a_tr = false, b_tr = false;       // layout of the chunk held in ra / rb
     int a_rows = 0;
+    static_assert(EA <= 32 && EB <= 32, "mask width");
 
     // global -> registers: the operands of chunk ch
     auto load = [&](const Chunk& ch) {
-        const Group gr = groups[ch.g];
+        const Group gr = R.group(ch.g);
         if (ch.kind == CH_XU) {
             const T* p = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
             const int ld = gr.ldx, rows = tk.m, K = gr.mu;
             const bool tr = (gr.flags & G_TRANS_X) != 0;
-            const T scale = (T)gr.x_coef;
             const int nel = nrm * 256;
+            uint32_t ok = 0;
 #pragma unroll
             for (int i = 0; i < EA; ++i) {
                 const int e = tid + i * NT;
                 int row, kk;
                 chunk_elem(e, !tr, row, kk);
                 const int k = ch.k0 + kk;
-                const uint32_t off = tr ? (uint32_t)(k * ld + row) : (uint32_t)(row * ld + k);
-                ra[i] = (e < nel && row < rows && k < K) ? scale * ld_at(p, off) : T(0);
+                const bool v = e < nel && row < rows && k < K;
+                ra[i] = ld_at(p, v ? (tr ? (uint32_t)(k * ld + row) : (uint32_t)(row * ld + k)) : 0u);
+                ok |= (uint32_t)v << i;
             }
+            a_ok = ok;
+            a_scale = (T)gr.x_coef;
             a_tr = tr;
             a_rows = rows;
             return;
         }
-        const Contrib ct = contribs[ch.c];
-        const T alpha = (T)ct.alpha;
+        const Contrib ct = R.contrib(ch.c);
         if (ch.kind == CH_AB) {
             const T* p = base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
             const T* q = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int lda = ct.lda, ldb = ct.ldb, rows = gr.mu, K = ct.k;
             const int nel = ((rows + 15) >> 4) * 256;
+            uint32_t ok = 0;
 #pragma unroll
             for (int i = 0; i < EA; ++i) {
                 const int e = tid + i * NT;
                 int row, kk;
                 chunk_elem(e, !ta, row, kk);
                 const int k = ch.k0 + kk;
-                const uint32_t off = ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k);
-                ra[i] = (e < nel && row < rows && k < K) ? alpha * ld_at(p, off) : T(0);
+                const bool v = e < nel && row < rows && k < K;
+                ra[i] = ld_at(p, v ? (ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k)) : 0u);
+                ok |= (uint32_t)v << i;
             }
+            a_ok = ok;
+            ok = 0;
 #pragma unroll
             for (int i = 0; i < EB; ++i) {
                 int col, kk;
                 chunk_elem(tid + i * NT, tb, col, kk);
                 const int k = ch.k0 + kk;
                 const int c = tk.col0 + col;
-                const uint32_t off = tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c);
-                rb[i] = (col < ncv && k < K) ? ld_at(q, off) : T(0);
+                const bool v = col < ncv && k < K;
+                rb[i] = ld_at(q, v ? (tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c)) : 0u);
+                ok |= (uint32_t)v << i;
             }
+            b_ok = ok;
+            a_scale = (T)ct.alpha;
+            b_scale = T(1);
             a_tr = ta;
             a_rows = rows;
             b_tr = tb;
@@ -224,31 +330,32 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                          : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
         const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
         const int ld = ida ? ct.ldb : ct.lda;
+        uint32_t ok = 0;
 #pragma unroll
         for (int i = 0; i < EB; ++i) {
             int col, kk;
             chunk_elem(tid + i * NT, tp, col, kk);
             const int row = ch.k0 + kk;
             const int c = tk.col0 + col;
-            T x = 0;
-            if (col < ncv && row < gr.mu) {
-                if (ida && idb)   // a_off: diagonal offset of the identity
-                    x = ((int64_t)row + ct.a_off == c) ? alpha : T(0);
-                else
-                    x = alpha * ld_at(p, tp ? (uint32_t)(c * ld + row) : (uint32_t)(row * ld + c));
-            }
-            rb[i] = x;
+            const bool v = col < ncv && row < gr.mu;
+            if (ida && idb)   // a_off: diagonal offset of the identity
+                rb[i] = ((int64_t)row + ct.a_off == c) ? T(1) : T(0);
+            else
+                rb[i] = ld_at(p, v ? (tp ? (uint32_t)(c * ld + row) : (uint32_t)(row * ld + c)) : 0u);
+            ok |= (uint32_t)v << i;
         }
+        b_ok = ok;
+        b_scale = (T)ct.alpha;
         b_tr = tp;
     };
-    // registers -> LDS buffer b
+    // registers -> LDS buffer b (masking and scaling here, after the loads landed)
     auto store = [&](const Chunk& ch, int b) {
         if (ch.kind != CH_XU) {
 #pragma unroll
             for (int i = 0; i < EB; ++i) {
                 int col, kk;
                 chunk_elem(tid + i * NT, b_tr, col, kk);
-                sB[b][col * LD + (ch.kind == CH_ID ? xu_pos<T>(kk) : kk)] = rb[i];
+                sB[b][col * LD + (ch.kind == CH_ID ? xu_pos<T>(kk) : kk)] = ((b_ok >> i) & 1) ? b_scale * rb[i] : T(0);
             }
         }
         if (ch.kind != CH_ID) {
@@ -259,47 +366,37 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                 if (e < nel) {
                     int row, kk;
                     chunk_elem(e, !a_tr, row, kk);
-                    sA[b][row * LD + (ch.kind == CH_XU ? xu_pos<T>(kk) : kk)] = ra[i];
+                    sA[b][row * LD + (ch.kind == CH_XU ? xu_pos<T>(kk) : kk)] =
+                        ((a_ok >> i) & 1) ? a_scale * ra[i] : T(0);
                 }
             }
         }
     };
 
-    Chunk cur = first_chunk(groups, contribs, tk.g0, tk.g1);
+    Chunk cur = first_chunk(R, tk.g0, tk.g1);
     if (cur.g >= 0) load(cur);
     int buf = 0, gcur = -1;
-    bool xid_pending = false;   // identity-X part of group gcur not yet added
-    auto add_xid = [&](int g) {
-        const T xi = (T)groups[g].xid_coef;
-        if (xi != T(0)) {
-#pragma unroll
-            for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
-        }
-    };
-    auto rotate_u = [&]() {
-        const V4 t = U[0];
-#pragma unroll
-        for (int i = 0; i < kRT - 1; ++i) U[i] = U[i + 1];
-        U[kRT - 1] = t;
-    };
+    T xi = 0;   // identity-X coefficient of group gcur still to be applied (0 once applied)
     while (cur.g >= 0) {
         store(cur, buf);
         __syncthreads();   // chunk cur complete in LDS; the buffer written next is free
-        const Chunk nx = next_chunk(groups, contribs, cur, tk.g1);
+        const Chunk nx = next_chunk(R, cur, tk.g1);
         if (nx.g >= 0) load(nx);   // in flight during the MFMAs below
         if (cur.g != gcur) {
-            if (xid_pending) add_xid(gcur);
+#pragma unroll
+            for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
 #pragma unroll
             for (int i = 0; i < kRT; ++i) U[i] = V4{0, 0, 0, 0};
             gcur = cur.g;
-            xid_pending = true;
+            xi = (T)R.group(gcur).xid_coef;
         }
         const T* A = sA[buf];
         const T* Bs = sB[buf];
         if (cur.kind == CH_AB) {
-            const int nru = (groups[cur.g].mu + 15) >> 4;
+            const int nru = (R.gmu(cur.g) + 15) >> 4;
             T bf[4];
             lds_read4(Bs + mycol * LD + 4 * lk, bf);
+            // row tiles in pairs: fragments of at most two tiles live at once
 #pragma unroll
             for (int i = 0; i < kRT; ++i) {
                 if (i >= nru) continue;
@@ -307,34 +404,40 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                 lds_read4(A + (16 * i + lr) * LD + 4 * lk, af);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(af[s], bf[s], U[i]);
+                if (i & 1) __builtin_amdgcn_sched_barrier(0);
             }
         } else if (cur.kind == CH_XU) {
-            if (xid_pending) {   // U is complete at the first X . U chunk
-                add_xid(gcur);
-                xid_pending = false;
-            }
+            if (cur.k0 == 0) {   // U is complete at the first X . U chunk
 #pragma unroll
-            for (int i = 0; i < kRT; ++i) {
-                if (i >= nrm) continue;
-                T xf[4];
-                lds_read4(A + (16 * i + lr) * LD + 4 * lk, xf);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[s], U[0][s], acc[i]);
+                for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
+                xi = 0;
             }
-            rotate_u();
+            tile_switch(cur.k0 >> 4, [&](auto J) {
+                constexpr int j = decltype(J)::value;
+#pragma unroll
+                for (int i = 0; i < kRT; ++i) {
+                    if (i >= nrm) continue;
+                    T xf[4];
+                    lds_read4(A + (16 * i + lr) * LD + 4 * lk, xf);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[s], U[j][s], acc[i]);
+                    if (i & 1) __builtin_amdgcn_sched_barrier(0);
+                }
+            });
         } else {
             T f[4];
             lds_read4(Bs + mycol * LD + 4 * lk, f);
+            tile_switch(cur.k0 >> 4, [&](auto J) {
+                constexpr int j = decltype(J)::value;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) U[0][v] += f[v];
-            rotate_u();
-            if (nx.g != cur.g || nx.c != cur.c || nx.kind != CH_ID)   // last chunk of the contribution
-                for (int r = (groups[cur.g].mu + 15) >> 4; r < kRT; ++r) rotate_u();
+                for (int v = 0; v < 4; ++v) U[j][v] += f[v];
+            });
         }
         buf ^= 1;
         cur = nx;
     }
-    if (xid_pending) add_xid(gcur);
+#pragma unroll
+    for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
 
     const int cbuf = tk.cbuf & 15;
     const bool accum = (tk.cbuf >> 8) & 1;
@@ -369,13 +472,16 @@ template <typename T, int RT, int CT> struct WaveOcc {
     static constexpr int waves = sizeof(T) == 4 ? (RT * CT == 1 ? 6 : 5) : (RT * CT <= 2 ? 4 : 3);
 };
 
-template <typename T, int RT, int CT>
+template <typename T, int RT, int CT, bool LR>
 __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(Bases<T> Bargs, const Task* __restrict__ tasks, int ntask,
                                                    const Group* __restrict__ groups,
                                                    const Contrib* __restrict__ contribs) {
     using V4 = typename Mfma<T>::v4;
+    __shared__ Group sG[LR ? 4 : 1][LR ? kRecG : 1];
+    __shared__ Contrib sC[LR ? 4 : 1][LR ? kRecC : 1];
     (void)Bargs;
-    const int ti = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    const int ti = blockIdx.x * 4 + wv;
     if (ti >= ntask) return;
     const int lane = threadIdx.x & 63;
     const int lr = lane & 15;
@@ -383,6 +489,16 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
     const Task tk = tasks[ti];
     const int vec = blockIdx.y;
     const int ncv = min(tk.ncol, tk.n - tk.col0);
+    Recs<LR> R;
+    if constexpr (LR) {   // each wave stages its own task's records; in-order LDS within a wave
+        const int cb = stage_records(groups, contribs, tk.g0, tk.g1, sG[wv], sC[wv], lane, 64);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        R = Recs<true>{sG[wv], sC[wv], tk.g0, cb};
+    } else {
+        R = Recs<false>{groups, contribs};
+    }
 
     V4 acc[RT][CT];
 #pragma unroll
@@ -391,7 +507,7 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
         for (int j = 0; j < CT; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
     for (int g = tk.g0; g < tk.g1; ++g) {
-        const Group gr = groups[g];
+        const Group gr = R.group(g);
         const int mu = gr.mu;
         V4 U[RT][CT];
 #pragma unroll
@@ -399,7 +515,7 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
 #pragma unroll
             for (int j = 0; j < CT; ++j) U[i][j] = V4{0, 0, 0, 0};
         for (int c = gr.c0; c < gr.c1; ++c) {
-            const Contrib ct = contribs[c];
+            const Contrib ct = R.contrib(c);
             const T alpha = (T)ct.alpha;
             if (is_identity(ct.flags)) {
                 const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
@@ -407,6 +523,8 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
                                  : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
                 const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
                 const int ld = ida ? ct.ldb : ct.lda;
+                // loads first (clamped to offset 0 when out of range), masks after
+                T x[RT][CT][4];
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
 #pragma unroll
@@ -416,16 +534,23 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             const int row = 16 * i + Mfma<T>::row(lk, v);
-                            T x = 0;
-                            if (row < mu && col < ncv) {
-                                if (ida && idb)
-                                    x = ((int64_t)row + ct.a_off == gc) ? alpha : T(0);
-                                else
-                                    x = alpha * ld_at(P, tp ? (uint32_t)(gc * ld + row) : (uint32_t)(row * ld + gc));
-                            }
-                            U[i][j][v] += x;
+                            const bool ok = row < mu && col < ncv;
+                            if (ida && idb)
+                                x[i][j][v] = ((int64_t)row + ct.a_off == gc) ? T(1) : T(0);
+                            else
+                                x[i][j][v] = ld_at(P, ok ? (tp ? (uint32_t)(gc * ld + row) : (uint32_t)(row * ld + gc)) : 0u);
                         }
                     }
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+#pragma unroll
+                    for (int j = 0; j < CT; ++j)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 16 * i + Mfma<T>::row(lk, v);
+                            const bool ok = row < mu && 16 * j + lr < ncv;
+                            U[i][j][v] += ok ? alpha * x[i][j][v] : T(0);
+                        }
                 continue;
             }
             const T* Ap = base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
@@ -433,6 +558,7 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
             for (int k0 = 0; k0 < K; k0 += 16) {
+                // all fragment loads of the chunk first (clamped), masks at use
                 T fa[RT][4], fb[CT][4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
@@ -440,18 +566,23 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
 #pragma unroll
                     for (int i = 0; i < RT; ++i) {
                         const int row = 16 * i + lr;
-                        fa[i][s] = (row < mu && k < K)
-                                       ? alpha * ld_at(Ap, ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k))
-                                       : T(0);
+                        const bool ok = row < mu && k < K;
+                        fa[i][s] = ld_at(Ap, ok ? (ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k)) : 0u);
                     }
 #pragma unroll
                     for (int j = 0; j < CT; ++j) {
-                        const int col = 16 * j + lr;
-                        const int gc = tk.col0 + col;
-                        fb[j][s] = (col < ncv && k < K)
-                                       ? ld_at(Bp, tb ? (uint32_t)(gc * ldb + k) : (uint32_t)(k * ldb + gc))
-                                       : T(0);
+                        const int gc = tk.col0 + 16 * j + lr;
+                        const bool ok = 16 * j + lr < ncv && k < K;
+                        fb[j][s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gc * ldb + k) : (uint32_t)(k * ldb + gc)) : 0u);
                     }
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int k = k0 + 4 * lk + s;
+#pragma unroll
+                    for (int i = 0; i < RT; ++i) fa[i][s] = (16 * i + lr < mu && k < K) ? alpha * fa[i][s] : T(0);
+#pragma unroll
+                    for (int j = 0; j < CT; ++j) fb[j][s] = (16 * j + lr < ncv && k < K) ? fb[j][s] : T(0);
                 }
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
@@ -475,10 +606,15 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
 #pragma unroll
                     for (int i = 0; i < RT; ++i) {
                         const int row = 16 * i + lr;
-                        xf[i][s] = (row < tk.m && k < mu)
-                                       ? xc * ld_at(Xp, tx ? (uint32_t)(k * ldx + row) : (uint32_t)(row * ldx + k))
-                                       : T(0);
+                        const bool ok = row < tk.m && k < mu;
+                        xf[i][s] = ld_at(Xp, ok ? (tx ? (uint32_t)(k * ldx + row) : (uint32_t)(row * ldx + k)) : 0u);
                     }
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int k = 16 * q + Mfma<T>::row(lk, s);
+#pragma unroll
+                    for (int i = 0; i < RT; ++i) xf[i][s] = (16 * i + lr < tk.m && k < mu) ? xc * xf[i][s] : T(0);
                 }
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
@@ -518,42 +654,49 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
         }
 }
 
-template <typename T>
-static int launch_chain(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
-                        int nvec, void* stream) {
-    if (ntask <= 0) return 0;
-    hipStream_t s = (hipStream_t)stream;
+template <typename T, bool LR>
+static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
+                          int nvec, hipStream_t s) {
     if (cls >= kNumTileClass) {   // wave classes: four tasks per workgroup
         const dim3 grid((ntask + 3) / 4, nvec), block(256);
         switch (cls - kNumTileClass) {
-            case 0: hipLaunchKernelGGL((wave_kernel<T, 1, 1>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 1: hipLaunchKernelGGL((wave_kernel<T, 1, 2>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 2: hipLaunchKernelGGL((wave_kernel<T, 2, 1>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 3: hipLaunchKernelGGL((wave_kernel<T, 2, 2>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 0: hipLaunchKernelGGL((wave_kernel<T, 1, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 1: hipLaunchKernelGGL((wave_kernel<T, 1, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 2: hipLaunchKernelGGL((wave_kernel<T, 2, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 3: hipLaunchKernelGGL((wave_kernel<T, 2, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
             default: return (int)hipErrorInvalidValue;
         }
         return (int)hipGetLastError();
     }
     const dim3 grid(ntask, nvec), block(64 * (cls + 1));
     switch (cls) {
-        case 0: hipLaunchKernelGGL((tile_kernel<T, 1>), grid, block, 0, s, b, t, g, c); break;
-        case 1: hipLaunchKernelGGL((tile_kernel<T, 2>), grid, block, 0, s, b, t, g, c); break;
-        case 2: hipLaunchKernelGGL((tile_kernel<T, 3>), grid, block, 0, s, b, t, g, c); break;
-        case 3: hipLaunchKernelGGL((tile_kernel<T, 4>), grid, block, 0, s, b, t, g, c); break;
-        case 4: hipLaunchKernelGGL((tile_kernel<T, 5>), grid, block, 0, s, b, t, g, c); break;
-        case 5: hipLaunchKernelGGL((tile_kernel<T, 6>), grid, block, 0, s, b, t, g, c); break;
+        case 0: hipLaunchKernelGGL((tile_kernel<T, 1, LR>), grid, block, 0, s, b, t, g, c); break;
+        case 1: hipLaunchKernelGGL((tile_kernel<T, 2, LR>), grid, block, 0, s, b, t, g, c); break;
+        case 2: hipLaunchKernelGGL((tile_kernel<T, 3, LR>), grid, block, 0, s, b, t, g, c); break;
+        case 3: hipLaunchKernelGGL((tile_kernel<T, 4, LR>), grid, block, 0, s, b, t, g, c); break;
+        case 4: hipLaunchKernelGGL((tile_kernel<T, 5, LR>), grid, block, 0, s, b, t, g, c); break;
+        case 5: hipLaunchKernelGGL((tile_kernel<T, 6, LR>), grid, block, 0, s, b, t, g, c); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
 }
 
-int launch_chain_f64(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
-                     const Bases<double>& b, int nvec, void* stream) {
-    return launch_chain<double>(cls, t, ntask, g, c, b, nvec, stream);
+template <typename T>
+static int launch_chain(int cls, bool lds_records, const Task* t, int ntask, const Group* g, const Contrib* c,
+                        const Bases<T>& b, int nvec, void* stream) {
+    if (ntask <= 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    return lds_records ? launch_chain_t<T, true>(cls, t, ntask, g, c, b, nvec, s)
+                       : launch_chain_t<T, false>(cls, t, ntask, g, c, b, nvec, s);
 }
-int launch_chain_f32(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+
+int launch_chain_f64(int cls, bool lds_records, const Task* t, int ntask, const Group* g, const Contrib* c,
+                     const Bases<double>& b, int nvec, void* stream) {
+    return launch_chain<double>(cls, lds_records, t, ntask, g, c, b, nvec, stream);
+}
+int launch_chain_f32(int cls, bool lds_records, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<float>& b, int nvec, void* stream) {
-    return launch_chain<float>(cls, t, ntask, g, c, b, nvec, stream);
+    return launch_chain<float>(cls, lds_records, t, ntask, g, c, b, nvec, stream);
 }
 
 template <typename T>

@@ -2,7 +2,7 @@
 //
 // Everything heavy (blocking + transformation, the normal->complementary
 // transform, the integral-weighted operator sums and H_eff psi) is expressed
-// as one kind of work: an output tile C (up to 96 rows x 96 columns of a
+// as one kind of work: an output tile C (up to 80 rows x 96 columns of a
 // sector block) accumulated as
 //
 //     C = sum_groups [ x_coef * X_g . U_g + xid_coef * U_g ],
@@ -22,7 +22,13 @@
 
 namespace dmrgk {
 
-constexpr int kMaxRows = 96;     // rows of an output tile, and of U (inner dimension of X . U)
+// Rows of an output tile and of U (inner dimension of X . U): five MFMA row
+// tiles, so that the FP32 accumulators of the wide tile kernels stay within
+// 128 registers (four waves per SIMD); taller tiles are split exactly.
+#ifndef DMRG_MAX_ROWS
+#define DMRG_MAX_ROWS 80
+#endif
+constexpr int kMaxRows = DMRG_MAX_ROWS;
 constexpr int kMaxCols = 96;     // columns of an output tile
 constexpr int kMaxBuf = 9;       // buffer 8: partial tiles of split tasks
 
@@ -78,10 +84,16 @@ inline int task_class(int rows, int ncol) {
 inline int class_rows(int cls) { return cls < kNumTileClass ? kMaxRows : 16 * ((cls - kNumTileClass) / 2 + 1); }
 inline int class_cols(int cls) { return cls < kNumTileClass ? 16 * (cls + 1) : 16 * ((cls - kNumTileClass) % 2 + 1); }
 
+// Records per task that fit the LDS staging of the kernels: a work list
+// whose every task has at most kRecG groups, whose contributions (at most
+// kRecC) are contiguous, runs with lds_records = true.
+constexpr int kRecG = 48;
+constexpr int kRecC = 128;
+
 // launchers (return hipError_t as int)
-int launch_chain_f64(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f64(int cls, bool lds_records, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<double>& b, int nvec, void* stream);
-int launch_chain_f32(int cls, const Task* t, int ntask, const Group* g, const Contrib* c,
+int launch_chain_f32(int cls, bool lds_records, const Task* t, int ntask, const Group* g, const Contrib* c,
                      const Bases<float>& b, int nvec, void* stream);
 
 // A task whose group range is split writes each chunk's tile to its own slot

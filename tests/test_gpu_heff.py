@@ -243,3 +243,51 @@ def test_c3_full_size_invariants():
     assert abs(a - b) <= 1e-12 * nrm
     assert lin <= 1e-13
     assert e32 <= 1e-5
+
+
+def test_profile_matches_apply_and_counts_flops():
+    """The timed product (one event pair per launch) equals a plain product bitwise,
+    and its per-launch useful flops cover at least F_alg."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(12, 12, 0, 70, 16)
+    ctx, L, R, H, keep = _step(p, arena=2 << 30)
+    x = torch.from_numpy(p.psi.copy()).cuda()
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    H.apply(x, y1)
+    launches = H.profile(x, y2)
+    torch.cuda.synchronize()
+    F = H.flops
+    _close(H, L, R, ctx)
+    assert torch.equal(y1, y2)
+    assert len(launches) == d.DMRG_HEFF_LAUNCHES
+    assert all(ms >= 0 for _, ms, _ in launches)
+    assert sum(fl for _, _, fl in launches) >= F
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_vectors_beyond_root_count(prec):
+    """n_vec above n_roots runs in batches of n_roots (the partial-tile buffer's
+    capacity); each vector's product equals its single-vector product."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(12, 11, 1, 50, 71)
+    ctx, L, R, H, keep = _step(p, arena=2 << 30, n_roots=2)
+    n = H.dim
+    X = synth.random_vectors(n, 5, 17)
+    dt = torch.float64 if prec == d.DMRG_PREC_F64 else torch.float32
+    xb = torch.from_numpy(X.ravel().copy()).to(dt).cuda()
+    yb = torch.empty_like(xb)
+    H.apply(xb, yb, prec, 5)
+    singles = []
+    for i in range(5):
+        y = torch.empty(n, dtype=dt, device="cuda")
+        H.apply(xb[i * n:(i + 1) * n].contiguous(), y, prec)
+        singles.append(y)
+    torch.cuda.synchronize()
+    ok = all(torch.equal(yb[i * n:(i + 1) * n], singles[i]) for i in range(5))
+    ref = blockops.MiddleHeff(p, "CN").apply(X[3])
+    e3 = _rel(yb[3 * n:4 * n].double().cpu().numpy(), ref)
+    _close(H, L, R, ctx)
+    assert ok
+    assert e3 <= (1e-12 if prec == d.DMRG_PREC_F64 else 1e-5)
