@@ -30,11 +30,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 def launch_kernel_name(kind: int, prec: str = "float") -> str:
     """Kernel of launch slot `kind` of one H_eff product (see dmrg_heff_profile)."""
-    if kind < 6:
-        return f"tile_kernel<{prec}, {kind + 1}>"
-    if kind < 10:
-        rt, ct = divmod(kind - 6, 2)
-        return f"wave_kernel<{prec}, {rt + 1}, {ct + 1}>"
+    slot, lr = kind & 255, "true" if kind & 256 else "false"
+    if slot < 6:
+        return f"tile_kernel<{prec}, {slot + 1}, {lr}>"
+    if slot < 10:
+        rt, ct = divmod(slot - 6, 2)
+        return f"wave_kernel<{prec}, {rt + 1}, {ct + 1}, {lr}>"
     return f"reduce_kernel<{prec}>"
 
 
@@ -120,7 +121,10 @@ def main():
     prob = synth.config_problem(args.workload)
     n_elec = prob.target[0] + prob.target[1]
     two_sz = prob.target[0] - prob.target[1]
-    scheme = "NC" if prob.n_proc > 1 else "CN"
+    # right block: CN normal operators + the middle transform (the mixed NC/CN form);
+    # the sub-Hamiltonian share takes the same route on one GPU, where the NC right
+    # block of its owned pairs would need about twice the arena (both give one sigma)
+    scheme = "CN"
     # inputs resident in HBM before timing
     ctx = dmrg.Context(int(W["arena_gb"] * (1 << 30)))
     li = [dmrg.Isometry(u, dev) for u in prob.left_iso]

@@ -824,7 +824,7 @@ int32_t dmrg_heff_profile(dmrg_heff* H, int32_t precision, const void* psi, void
     for (int i = 0; i <= dmrgk::kNumClass; ++i) {
         ms[i] = t[i];
         flops[i] = i < dmrgk::kNumClass ? H->work.useful[i] : 0.0;
-        kind[i] = i;
+        kind[i] = i | (H->work.lds_records && i < dmrgk::kNumClass ? 256 : 0);
     }
     return dmrgk::kNumClass + 1;
 }

@@ -261,6 +261,7 @@ def test_profile_matches_apply_and_counts_flops():
     _close(H, L, R, ctx)
     assert torch.equal(y1, y2)
     assert len(launches) == d.DMRG_HEFF_LAUNCHES
+    assert [k & 255 for k, _, _ in launches] == list(range(d.DMRG_HEFF_LAUNCHES))
     assert all(ms >= 0 for _, ms, _ in launches)
     assert sum(fl for _, _, fl in launches) >= F
 
