@@ -118,13 +118,19 @@ def main():
     W = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    note(f"generating the {args.workload} inputs")
     prob = synth.config_problem(args.workload)
+    note("inputs ready")
     n_elec = prob.target[0] + prob.target[1]
     two_sz = prob.target[0] - prob.target[1]
     # right block: CN normal operators + the middle transform (the mixed NC/CN form);
-    # the sub-Hamiltonian share takes the same route on one GPU, where the NC right
-    # block of its owned pairs would need about twice the arena (both give one sigma)
-    scheme = "CN"
+    # a sub-Hamiltonian share keeps NC complementary operators of its owned pairs
+    # only (the CN right block of all pairs would not fit one GPU at 108 orbitals)
+    scheme = "NC" if prob.n_proc > 1 else "CN"
     # inputs resident in HBM before timing
     ctx = dmrg.Context(int(W["arena_gb"] * (1 << 30)))
     li = [dmrg.Isometry(u, dev) for u in prob.left_iso]
@@ -144,10 +150,13 @@ def main():
     def build():
         ctx.set_integrals(prob.h1e, prob.g2e, n_elec, two_sz, prob.e_core, prob.n_proc, prob.proc_id)
         L = ctx.build_block(dmrg.DMRG_LEFT, li, dmrg.DMRG_SCHEME_NC)
+        note("left block built")
         R = ctx.build_block(dmrg.DMRG_RIGHT, ri, dmrg.DMRG_SCHEME_CN if scheme == "CN" else dmrg.DMRG_SCHEME_NC)
+        note("right block built")
         if scheme == "CN":
             ctx.normal_to_complementary(R)
         H = ctx.heff_create(L, R, roots)
+        note("H_eff work list built")
         return L, R, H
 
     def timed_apply(H, prec, n):
@@ -192,6 +201,7 @@ def main():
         e, st = H.davidson(psi, roots, precision=dmrg.DMRG_PREC_F32, fixed_iters=W["iters"],
                            max_subspace=max(24, 4 * roots))
         td = time.perf_counter()
+        note(f"Davidson done ({(td - tb):.1f} s)")
         t32 = timed_apply(H, dmrg.DMRG_PREC_F32, args.napply)
         t64 = timed_apply(H, dmrg.DMRG_PREC_F64, args.napply)
         N = H.renormalize(ni)

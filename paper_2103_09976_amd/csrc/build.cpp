@@ -320,8 +320,9 @@ void grow_right_compl(const Ctx* C, const OpSetImpl& Y, int n, const std::vector
 // same family of `old` (same orientation and sign rule) are replaced by one
 // integral-weighted sum (GEMM over the operator index); identity components of
 // one transition are merged.
-void compact(std::vector<TransOp>& ops, const OpSetImpl& old, WSumPlan& plan) {
+void compact(std::vector<TransOp>& ops, const OpSetImpl& old, WSumPlan& plan, std::vector<int>* req_begin) {
     for (TransOp& T : ops) {
+        if (req_begin) req_begin->push_back((int)plan.reqs.size());
         std::map<std::tuple<int, int, int, int, int>, std::vector<int>> grp;
         std::map<std::tuple<int, int, int>, double> idc;
         std::vector<Comp> out;
@@ -373,13 +374,16 @@ void compact(std::vector<TransOp>& ops, const OpSetImpl& old, WSumPlan& plan) {
             }
         T.comps.swap(out);
     }
+    if (req_begin) req_begin->push_back((int)plan.reqs.size());
 }
 
-void resolve(std::vector<TransOp>& ops, const WSumPlan& plan, const OpSetImpl& temps) {
-    for (TransOp& T : ops)
-        for (Comp& c : T.comps)
+void resolve(std::vector<TransOp>& ops, const WSumPlan& plan, const OpSetImpl& temps, size_t i0, size_t i1,
+             int rbase) {
+    i1 = std::min(i1, ops.size());
+    for (size_t i = i0; i < i1; ++i)
+        for (Comp& c : ops[i].comps)
             if (c.ref.type == 2) {
-                const auto o = plan.out[c.ref.idx];
+                const auto o = plan.out[c.ref.idx - rbase];
                 c.ref.type = 1;
                 c.ref.set = &temps;
                 c.ref.fam = o.first;
@@ -389,8 +393,8 @@ void resolve(std::vector<TransOp>& ops, const WSumPlan& plan, const OpSetImpl& t
 
 // ---------------------------------------------------------------------------
 // transformation: O_new[q' <- q] = sum_{(s',s)} U_{q',s'}^T (sum_k c_k Z_k) U_{q,s}
-static dmrg_status renormalize_ops(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const Iso& iso,
-                                   const Grown& G, OpSetImpl& nw, void* stream) {
+// the new set: one operator per grown operator, in the new basis (allocated)
+static dmrg_status layout_new_set(Ctx* C, const Iso& iso, const Grown& G, OpSetImpl& nw) {
     nw.basis = iso.nb;
     nw.basis.index();
     nw.skels.clear();
@@ -398,12 +402,17 @@ static dmrg_status renormalize_ops(Ctx* C, const OpSetImpl& old, const OpSetImpl
     nw.lookup.clear();
     for (size_t i = 0; i < G.keys.size(); ++i)
         nw.add_op(G.kinds[i], G.idx[i].first, G.idx[i].second, G.ops[i].dq, G.ops[i].par);
-    dmrg_status st = alloc_set(C, nw);
-    if (st != DMRG_OK) return st;
+    return alloc_set(C, nw);
+}
+
+// transformation of the grown operators i0..i1-1 into their rows of nw
+static dmrg_status renormalize_range(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const Iso& iso,
+                                     const Grown& G, size_t i0, size_t i1, OpSetImpl& nw, void* stream) {
+    dmrg_status st = DMRG_OK;
     WorkList wl;
     const Basis& ob = old.basis;
     const Basis& nb = nw.basis;
-    for (size_t i = 0; i < G.keys.size(); ++i) {
+    for (size_t i = i0; i < i1; ++i) {
         const auto fi = nw.lookup.at(G.keys[i]);
         const Family& F = nw.fams[fi.first];
         const Skel& S = nw.skels[F.skel];
@@ -457,6 +466,7 @@ static dmrg_status renormalize_ops(Ctx* C, const OpSetImpl& old, const OpSetImpl
                              (int)wl.groups.size());
         }
     }
+    if (wl.ntasks() == 0) return DMRG_OK;
     int64_t sz[dmrgk::kMaxBuf] = {0};
     sz[0] = old.elems;
     sz[1] = temps ? temps->elems : 0;
@@ -485,28 +495,55 @@ dmrg_status renormalize_grown(Ctx* C, const OpSetImpl& old, const OpSetImpl* tem
                               const Grown& G, OpSetImpl& nw, void* stream) {
     Iso iso;
     dmrg_status st = make_iso(old.basis, iso_desc, iso);
-    if (st != DMRG_OK) return st;
-    return renormalize_ops(C, old, temps, iso, G, nw, stream);
+    if (st == DMRG_OK) st = layout_new_set(C, iso, G, nw);
+    if (st == DMRG_OK) st = renormalize_range(C, old, temps, iso, G, 0, G.ops.size(), nw, stream);
+    return st;
 }
 
-// one growth step + transformation: old -> nw (old and the temporaries are released)
+// One growth step + transformation: old -> nw.  The integral-weighted sums of
+// the grown operators (temporaries in the old basis) are formed and consumed
+// in batches of operators whose temporaries fit half of the free arena, so
+// the transient memory stays bounded when thousands of operators grow at once.
 dmrg_status grow_and_renormalize(Ctx* C, OpSetImpl& old, Grown& G, const dmrg_bsm* iso_desc,
                                  OpSetImpl& nw, void* stream) {
     WSumPlan plan;
-    compact(G.ops, old, plan);
-    OpSetImpl temps;
-    temps.basis = old.basis;
-    temps.kind = 2;
-    plan_wsums(old, plan, temps);
-    dmrg_status st = alloc_set(C, temps);
-    if (st != DMRG_OK) return st;
-    st = exec_wsums(C, old, plan, temps, stream);
-    if (st != DMRG_OK) { free_set(C, temps); return st; }
-    resolve(G.ops, plan, temps);
+    std::vector<int> rb;
+    compact(G.ops, old, plan, &rb);
     Iso iso;
-    st = make_iso(old.basis, iso_desc, iso);
-    if (st == DMRG_OK) st = renormalize_ops(C, old, &temps, iso, G, nw, stream);
-    free_set(C, temps);
+    dmrg_status st = make_iso(old.basis, iso_desc, iso);
+    if (st == DMRG_OK) st = layout_new_set(C, iso, G, nw);
+    if (st != DMRG_OK) return st;
+    // DMRG_GROW_BATCH_BYTES overrides the budget (tests use it to force small batches)
+    const char* env = std::getenv("DMRG_GROW_BATCH_BYTES");
+    const int64_t budget = env ? std::atoll(env)
+                               : std::max<int64_t>(int64_t(1) << 28, (C->arena.bytes - C->arena.used) / 2);
+    const size_t n = G.ops.size();
+    size_t i0 = 0;
+    while (i0 < n && st == DMRG_OK) {
+        size_t i1 = i0;
+        int64_t bytes = 0;
+        while (i1 < n) {
+            int64_t b = 0;
+            for (int r = rb[i1]; r < rb[i1 + 1]; ++r) b += old.fams[plan.reqs[r].fam].stride * (int64_t)sizeof(double);
+            if (i1 > i0 && bytes + b > budget) break;
+            bytes += b;
+            ++i1;
+        }
+        WSumPlan sub;
+        sub.reqs.assign(plan.reqs.begin() + rb[i0], plan.reqs.begin() + rb[i1]);
+        OpSetImpl temps;
+        temps.basis = old.basis;
+        temps.kind = 2;
+        plan_wsums(old, sub, temps);
+        st = alloc_set(C, temps);
+        if (st == DMRG_OK) st = exec_wsums(C, old, sub, temps, stream);
+        if (st == DMRG_OK) {
+            resolve(G.ops, sub, temps, i0, i1, rb[i0]);
+            st = renormalize_range(C, old, &temps, iso, G, i0, i1, nw, stream);
+        }
+        free_set(C, temps);
+        i0 = i1;
+    }
     return st;
 }
 

@@ -296,8 +296,11 @@ struct Grown {
 
 void grow_left(const Ctx* C, const OpSetImpl& X, int n, const std::vector<int>& outside, Grown& G);
 void grow_right_compl(const Ctx* C, const OpSetImpl& Y, int n, const std::vector<int>& before, Grown& G);
-void compact(std::vector<TransOp>& ops, const OpSetImpl& old, WSumPlan& plan);
-void resolve(std::vector<TransOp>& ops, const WSumPlan& plan, const OpSetImpl& temps);
+// req_begin (optional): request index at which each operator's sums start, plus the total
+void compact(std::vector<TransOp>& ops, const OpSetImpl& old, WSumPlan& plan, std::vector<int>* req_begin = nullptr);
+// operators i0..i1-1; their requests are plan.reqs[idx - rbase]
+void resolve(std::vector<TransOp>& ops, const WSumPlan& plan, const OpSetImpl& temps, size_t i0 = 0,
+             size_t i1 = SIZE_MAX, int rbase = 0);
 // transformation of grown operators (refs into old / temps) through an isometry
 dmrg_status renormalize_grown(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const dmrg_bsm* iso,
                               const Grown& G, OpSetImpl& nw, void* stream);
