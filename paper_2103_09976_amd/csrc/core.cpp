@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <tuple>
@@ -395,7 +396,7 @@ int task_class_of(const WorkList& w, const dmrgk::Task& t) {
 }
 
 void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int n, int g0, int g1,
-                      bool accumulate) {
+                      bool accumulate, int key) {
     if (m <= 0 || n <= 0) return;
     // near-equal column tiles of at most kMaxCols, widths in multiples of 16
     const int nt = (n + dmrgk::kMaxCols - 1) / dmrgk::kMaxCols;
@@ -411,6 +412,7 @@ void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int 
         t.g0 = g0;
         t.g1 = g1;
         t.cbuf = cbuf | (accumulate ? 256 : 0);
+        t.key = key;
         w.task[task_class_of(w, t)].push_back(t);
     }
 }
@@ -606,9 +608,16 @@ void balance_work(WorkList& w, int target_tasks) {
         }
     }
     w.partial_elems = poff;
+    const char* ord = std::getenv("DMRG_ORDER");
+    const bool by_key = ord && ord[0] == 'k';
     for (int c = 0; c < dmrgk::kNumClass; ++c) {
-        std::stable_sort(out[c].begin(), out[c].end(),
-                         [](const auto& x, const auto& y) { return x.first > y.first; });
+        if (by_key)
+            std::stable_sort(out[c].begin(), out[c].end(), [](const auto& x, const auto& y) {
+                return x.second.key != y.second.key ? x.second.key < y.second.key : x.first > y.first;
+            });
+        else
+            std::stable_sort(out[c].begin(), out[c].end(),
+                             [](const auto& x, const auto& y) { return x.first > y.first; });
         w.task[c].clear();
         for (auto& e : out[c]) w.task[c].push_back(e.second);
     }

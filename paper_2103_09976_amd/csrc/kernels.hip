@@ -194,6 +194,20 @@ __device__ inline void chunk_elem(int e, bool kcontig, int& row, int& kk) {
     else { row = ((e >> 8) << 4) | (e & 15); kk = (e >> 4) & 15; }
 }
 
+// Workgroups are dispatched to the eight XCDs round-robin.  With DMRG_XCD the
+// grid (a multiple of 8) is mapped so that XCD x runs the contiguous range
+// [x*per, (x+1)*per) of the ordered work list, keeping tasks that share
+// operands under one L2; -1 for workgroups past the end.
+#ifndef DMRG_XCD
+#define DMRG_XCD 0
+#endif
+__device__ inline int task_of_block(int b, int nblk) {
+    if (!DMRG_XCD) return b;
+    const int per = nblk >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+__host__ inline int grid_blocks(int n) { return DMRG_XCD ? (n + 7) / 8 * 8 : n; }
+
 // Minimum waves per SIMD each tile-kernel instantiation is compiled for
 // (caps registers at 512 / waves), chosen by measurement: FP32 tiles of three
 // or more slices fit 128 registers; narrower FP32 tiles and FP64 tiles need more.
@@ -212,17 +226,15 @@ __device__ inline const T* base_ptr(int buf, int vec) {
 template <typename T, int NCT, bool LR>
 __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Bases<T> Bargs,
                                                                                const Task* __restrict__ tasks,
+                                                                               int ntask,
                                                                                const Group* __restrict__ groups,
                                                                                const Contrib* __restrict__ contribs) {
     using V4 = typename Mfma<T>::v4;
     constexpr int NT = 64 * NCT;
     constexpr int LD = Lds<T>::ld;
     constexpr int AR = 16 * kRT;                  // rows of the A / X slot
-    constexpr int BR = 16 * NCT;                  // rows (tile columns) of the B slot
     constexpr int EA = (AR * kKC + NT - 1) / NT;  // A-slot elements per thread
-    constexpr int EB = BR * kKC / NT;             // B-slot elements per thread (4)
     __shared__ __attribute__((aligned(16))) T sA[2][AR * LD];
-    __shared__ __attribute__((aligned(16))) T sB[2][BR * LD];
     __shared__ Group sG[LR ? kRecG : 1];
     __shared__ Contrib sC[LR ? kRecC : 1];
     (void)Bargs;
@@ -232,7 +244,9 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     const int w = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
-    const Task tk = tasks[blockIdx.x];
+    const int bid = task_of_block(blockIdx.x, gridDim.x);
+    if (bid < 0 || bid >= ntask) return;   // padding of the XCD-mapped grid
+    const Task tk = tasks[bid];
     const int vec = blockIdx.y;
     const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
     const int nrm = (tk.m + 15) >> 4;                // output row tiles
@@ -253,12 +267,17 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     // (out-of-range elements read offset 0 of their block, which is always valid)
     // and masked when written to LDS, so no wait is needed before the MFMAs of
     // the current chunk.
-    T ra[EA], rb[EB];
-    uint32_t a_ok = 0, b_ok = 0;           // element i valid
-    T a_scale = 0, b_scale = 0;
-    bool a_tr = false, b_tr = false;       // layout of the chunk held in ra / rb
+    // The B operand (this wave's 16 columns) is not shared between waves: it is
+    // loaded straight into MFMA fragment registers (rb, in flight; rbc, the
+    // current chunk's copy) instead of through LDS.  For an A . B chunk lane
+    // (c, g) holds B[k0 + 4g + s][c] (s = 0..3); for an identity chunk it holds
+    // operand rows k0 + row(g, v) of column c, the accumulator layout of U.
+    T ra[EA], rb[4], rbc[4];
+    uint32_t a_ok = 0, b_ok = 0, b_okc = 0;   // element valid
+    T a_scale = 0, b_scale = 0, b_scalec = 0;
+    bool a_tr = false;                        // layout of the chunk held in ra
     int a_rows = 0;
-    static_assert(EA <= 32 && EB <= 32, "mask width");
+    static_assert(EA <= 32, "mask width");
 
     // global -> registers: the operands of chunk ch
     auto load = [&](const Chunk& ch) {
@@ -305,58 +324,48 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
             }
             a_ok = ok;
             ok = 0;
+            const int c = tk.col0 + mycol;
 #pragma unroll
-            for (int i = 0; i < EB; ++i) {
-                int col, kk;
-                chunk_elem(tid + i * NT, tb, col, kk);
-                const int k = ch.k0 + kk;
-                const int c = tk.col0 + col;
-                const bool v = col < ncv && k < K;
-                rb[i] = ld_at(q, v ? (tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c)) : 0u);
-                ok |= (uint32_t)v << i;
+            for (int s = 0; s < 4; ++s) {
+                const int k = ch.k0 + 4 * lk + s;
+                const bool v = mycol < ncv && k < K;
+                rb[s] = ld_at(q, v ? (tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c)) : 0u);
+                ok |= (uint32_t)v << s;
             }
             b_ok = ok;
             a_scale = (T)ct.alpha;
             b_scale = T(1);
             a_tr = ta;
             a_rows = rows;
-            b_tr = tb;
             return;
         }
-        // identity contribution: rows k0..k0+15 of alpha * operand (or of
-        // alpha * I shifted by a_off) into the B slot as [column][row]
+        // identity contribution: rows k0 + row(g, v) of alpha * operand (or of
+        // alpha * I shifted by a_off), this lane's column
         const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
         const T* p = ida ? base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off
                          : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
         const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
         const int ld = ida ? ct.ldb : ct.lda;
+        const int c = tk.col0 + mycol;
         uint32_t ok = 0;
 #pragma unroll
-        for (int i = 0; i < EB; ++i) {
-            int col, kk;
-            chunk_elem(tid + i * NT, tp, col, kk);
-            const int row = ch.k0 + kk;
-            const int c = tk.col0 + col;
-            const bool v = col < ncv && row < gr.mu;
+        for (int v4 = 0; v4 < 4; ++v4) {
+            const int row = ch.k0 + Mfma<T>::row(lk, v4);
+            const bool v = mycol < ncv && row < gr.mu;
             if (ida && idb)   // a_off: diagonal offset of the identity
-                rb[i] = ((int64_t)row + ct.a_off == c) ? T(1) : T(0);
+                rb[v4] = ((int64_t)row + ct.a_off == c) ? T(1) : T(0);
             else
-                rb[i] = ld_at(p, v ? (tp ? (uint32_t)(c * ld + row) : (uint32_t)(row * ld + c)) : 0u);
-            ok |= (uint32_t)v << i;
+                rb[v4] = ld_at(p, v ? (tp ? (uint32_t)(c * ld + row) : (uint32_t)(row * ld + c)) : 0u);
+            ok |= (uint32_t)v << v4;
         }
         b_ok = ok;
         b_scale = (T)ct.alpha;
-        b_tr = tp;
     };
     // registers -> LDS buffer b (masking and scaling here, after the loads landed)
     auto store = [&](const Chunk& ch, int b) {
-        if (ch.kind != CH_XU) {
+        if (ch.kind != CH_XU) {   // B fragments of this chunk: masked and scaled copy
 #pragma unroll
-            for (int i = 0; i < EB; ++i) {
-                int col, kk;
-                chunk_elem(tid + i * NT, b_tr, col, kk);
-                sB[b][col * LD + (ch.kind == CH_ID ? xu_pos<T>(kk) : kk)] = ((b_ok >> i) & 1) ? b_scale * rb[i] : T(0);
-            }
+            for (int s = 0; s < 4; ++s) rbc[s] = ((b_ok >> s) & 1) ? b_scale * rb[s] : T(0);
         }
         if (ch.kind != CH_ID) {
             const int nel = ((a_rows + 15) >> 4) * 256;
@@ -391,11 +400,9 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
             xi = (T)R.group(gcur).xid_coef;
         }
         const T* A = sA[buf];
-        const T* Bs = sB[buf];
         if (cur.kind == CH_AB) {
             const int nru = (R.gmu(cur.g) + 15) >> 4;
-            T bf[4];
-            lds_read4(Bs + mycol * LD + 4 * lk, bf);
+            const T* bf = rbc;
             // row tiles in pairs: fragments of at most two tiles live at once
 #pragma unroll
             for (int i = 0; i < kRT; ++i) {
@@ -425,12 +432,10 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                 }
             });
         } else {
-            T f[4];
-            lds_read4(Bs + mycol * LD + 4 * lk, f);
             tile_switch(cur.k0 >> 4, [&](auto J) {
                 constexpr int j = decltype(J)::value;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) U[j][v] += f[v];
+                for (int v = 0; v < 4; ++v) U[j][v] += rbc[v];
             });
         }
         buf ^= 1;
@@ -481,8 +486,9 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
     __shared__ Contrib sC[LR ? 4 : 1][LR ? kRecC : 1];
     (void)Bargs;
     const int wv = threadIdx.x >> 6;
-    const int ti = blockIdx.x * 4 + wv;
-    if (ti >= ntask) return;
+    const int bid = task_of_block(blockIdx.x, gridDim.x);
+    const int ti = bid * 4 + wv;
+    if (bid < 0 || ti >= ntask) return;   // also the padding of the XCD-mapped grid
     const int lane = threadIdx.x & 63;
     const int lr = lane & 15;
     const int lk = lane >> 4;
@@ -658,7 +664,7 @@ template <typename T, bool LR>
 static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
                           int nvec, hipStream_t s) {
     if (cls >= kNumTileClass) {   // wave classes: four tasks per workgroup
-        const dim3 grid((ntask + 3) / 4, nvec), block(256);
+        const dim3 grid(grid_blocks((ntask + 3) / 4), nvec), block(256);
         switch (cls - kNumTileClass) {
             case 0: hipLaunchKernelGGL((wave_kernel<T, 1, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
             case 1: hipLaunchKernelGGL((wave_kernel<T, 1, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
@@ -668,14 +674,14 @@ static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, con
         }
         return (int)hipGetLastError();
     }
-    const dim3 grid(ntask, nvec), block(64 * (cls + 1));
+    const dim3 grid(grid_blocks(ntask), nvec), block(64 * (cls + 1));
     switch (cls) {
-        case 0: hipLaunchKernelGGL((tile_kernel<T, 1, LR>), grid, block, 0, s, b, t, g, c); break;
-        case 1: hipLaunchKernelGGL((tile_kernel<T, 2, LR>), grid, block, 0, s, b, t, g, c); break;
-        case 2: hipLaunchKernelGGL((tile_kernel<T, 3, LR>), grid, block, 0, s, b, t, g, c); break;
-        case 3: hipLaunchKernelGGL((tile_kernel<T, 4, LR>), grid, block, 0, s, b, t, g, c); break;
-        case 4: hipLaunchKernelGGL((tile_kernel<T, 5, LR>), grid, block, 0, s, b, t, g, c); break;
-        case 5: hipLaunchKernelGGL((tile_kernel<T, 6, LR>), grid, block, 0, s, b, t, g, c); break;
+        case 0: hipLaunchKernelGGL((tile_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 1: hipLaunchKernelGGL((tile_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 2: hipLaunchKernelGGL((tile_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 3: hipLaunchKernelGGL((tile_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 4: hipLaunchKernelGGL((tile_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 5: hipLaunchKernelGGL((tile_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();

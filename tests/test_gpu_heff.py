@@ -292,3 +292,23 @@ def test_vectors_beyond_root_count(prec):
     _close(H, L, R, ctx)
     assert ok
     assert e3 <= (1e-12 if prec == d.DMRG_PREC_F64 else 1e-5)
+
+
+def test_mixed_vs_fp64_eight_roots():
+    """Block Davidson for 8 roots (odd N, S_z = 1/2): the FP32-mixed policy and the
+    FP64 path converge to the same energies within 1e-8 E_h."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(14, 13, 1, 90, 73)
+    ctx, L, R, H, keep = _step(p, arena=4 << 30, n_roots=8)
+    n = H.dim
+    start = synth.random_vectors(n, 8, 5).ravel().copy()
+    es = {}
+    for prec in (d.DMRG_PREC_F64, d.DMRG_PREC_F32):
+        psi = torch.from_numpy(start.copy()).cuda()
+        print(f"[gpu] 8-root davidson precision={prec}", flush=True)
+        e, st = H.davidson(psi, 8, tol=1e-6, precision=prec, switch_tol=1e-4, max_subspace=40, max_iter=400)
+        assert st["converged"] == 1, st
+        es[prec] = np.sort(e)
+    _close(H, L, R, ctx)
+    assert np.abs(es[0] - es[1]).max() <= 1e-8, (es[0], es[1])
