@@ -5,7 +5,6 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <tuple>
@@ -396,7 +395,7 @@ int task_class_of(const WorkList& w, const dmrgk::Task& t) {
 }
 
 void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int n, int g0, int g1,
-                      bool accumulate, int key) {
+                      bool accumulate) {
     if (m <= 0 || n <= 0) return;
     // near-equal column tiles of at most kMaxCols, widths in multiples of 16
     const int nt = (n + dmrgk::kMaxCols - 1) / dmrgk::kMaxCols;
@@ -412,7 +411,6 @@ void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int 
         t.g0 = g0;
         t.g1 = g1;
         t.cbuf = cbuf | (accumulate ? 256 : 0);
-        t.key = key;
         w.task[task_class_of(w, t)].push_back(t);
     }
 }
@@ -608,16 +606,9 @@ void balance_work(WorkList& w, int target_tasks) {
         }
     }
     w.partial_elems = poff;
-    const char* ord = std::getenv("DMRG_ORDER");
-    const bool by_key = ord && ord[0] == 'k';
     for (int c = 0; c < dmrgk::kNumClass; ++c) {
-        if (by_key)
-            std::stable_sort(out[c].begin(), out[c].end(), [](const auto& x, const auto& y) {
-                return x.second.key != y.second.key ? x.second.key < y.second.key : x.first > y.first;
-            });
-        else
-            std::stable_sort(out[c].begin(), out[c].end(),
-                             [](const auto& x, const auto& y) { return x.first > y.first; });
+        std::stable_sort(out[c].begin(), out[c].end(),
+                         [](const auto& x, const auto& y) { return x.first > y.first; });
         w.task[c].clear();
         for (auto& e : out[c]) w.task[c].push_back(e.second);
     }
@@ -693,7 +684,8 @@ dmrg_status validate_work(WorkList& w, const int64_t* size) {
         }
     }
     for (const dmrgk::Reduce& r : w.reduces) {
-        if (r.m < 1 || r.ncol < 1 || r.col0 < 0 || r.col0 + r.ncol > r.ldc || r.nslot < 1)
+        if (r.m < 1 || r.m > dmrgk::kMaxRows || r.ncol < 1 || r.ncol > dmrgk::kMaxCols || r.col0 < 0 ||
+            r.col0 + r.ncol > r.ldc || r.nslot < 1)
             return fail(DMRG_E_STATE, "work list: bad reduction shape");
         if (!in(r.cbuf & 15, r.c_off, r.c_off + (int64_t)(r.m - 1) * r.ldc + r.col0 + r.ncol - 1))
             return fail(DMRG_E_STATE, "work list: reduction output out of bounds");

@@ -256,7 +256,7 @@ double task_useful_flops(const WorkList& w, const dmrgk::Task& t);
 
 // emit the tasks of one output block (m x n at c_off) with the given group range
 void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int n, int g0, int g1,
-                      bool accumulate = false, int key = 0);
+                      bool accumulate = false);
 
 // ------------- weighted sums ------------------------------------------------
 // out (family in `temps`) = sum_k w_k * ops[k] of input family `fam` in `src`

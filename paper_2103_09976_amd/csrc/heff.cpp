@@ -551,7 +551,7 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
             }
             db.c1 = (int)Lc.dtm.size();
             Lc.dbl.push_back(db);
-            emit_block_tasks(wl, 3, O.off, O.mb, O.ma, O.mb, g0, (int)wl.groups.size(), false, O.b);
+            emit_block_tasks(wl, 3, O.off, O.mb, O.ma, O.mb, g0, (int)wl.groups.size());
         }
     };
     const size_t nblk = H->blocks.size();

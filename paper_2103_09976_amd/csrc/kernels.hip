@@ -40,9 +40,9 @@ template <> struct Mfma<float> {
 constexpr int kRT = kMaxRows / 16;   // row tiles of a task
 constexpr int kKC = 16;              // k per LDS chunk
 
-// LDS row stride (elements): 16-byte aligned rows whose 16-byte fragment
-// reads by 16 consecutive rows fall on distinct banks.
-template <typename T> struct Lds { static constexpr int ld = sizeof(T) == 4 ? kKC + 4 : kKC + 2; };
+// LDS row stride (elements) for a chunk of KC k: 16-byte aligned rows whose
+// 16-byte fragment reads by 16 consecutive rows fall on distinct banks.
+template <typename T, int KC> struct Lds { static constexpr int ld = sizeof(T) == 4 ? KC + 4 : KC + 2; };
 
 // Within a chunk, MFMA step s takes k = 4g + s from lane group g (g = l/16):
 // the four k of a lane are contiguous in an LDS row, read as one fragment.
@@ -171,14 +171,14 @@ __device__ inline Chunk first_chunk(const RC& R, int g, int g1) {
     return Chunk{-1, 0, 0, 0};
 }
 
-template <class RC>
+template <int KC, class RC>
 __device__ inline Chunk next_chunk(const RC& R, Chunk ch, int g1) {
     const Group gr = R.group(ch.g);
     if (ch.kind == CH_XU) {
-        if (ch.k0 + kKC < gr.mu) return Chunk{ch.g, 0, ch.k0 + kKC, CH_XU};
+        if (ch.k0 + KC < gr.mu) return Chunk{ch.g, 0, ch.k0 + KC, CH_XU};
     } else {
         const int extent = ch.kind == CH_AB ? R.ck(ch.c) : gr.mu;
-        if (ch.k0 + kKC < extent) return Chunk{ch.g, ch.c, ch.k0 + kKC, ch.kind};
+        if (ch.k0 + KC < extent) return Chunk{ch.g, ch.c, ch.k0 + KC, ch.kind};
         if (ch.c + 1 < gr.c1)
             return Chunk{ch.g, ch.c + 1, 0, is_identity(R.cflags(ch.c + 1)) ? CH_ID : CH_AB};
         if (gr.flags & G_HAS_X) return Chunk{ch.g, 0, 0, CH_XU};
@@ -186,32 +186,27 @@ __device__ inline Chunk next_chunk(const RC& R, Chunk ch, int g1) {
     return first_chunk(R, ch.g + 1, g1);
 }
 
-// Element e of a 16-wide chunk slot.  kcontig: 16 consecutive threads take
-// 16 consecutive inner indices (kk) of one row; otherwise 16 consecutive
-// rows of one kk.  Rows of the slot are 16 * (number of row tiles).
+// Element e of a KC-wide chunk slot (KC = 16 or 32).  kcontig: KC consecutive
+// threads take KC consecutive inner indices (kk) of one row; otherwise 16
+// consecutive rows of one kk.  Rows of the slot are 16 * (number of row tiles).
+template <int KC>
 __device__ inline void chunk_elem(int e, bool kcontig, int& row, int& kk) {
-    if (kcontig) { row = e >> 4; kk = e & 15; }
-    else { row = ((e >> 8) << 4) | (e & 15); kk = (e >> 4) & 15; }
+    constexpr int SH = KC == 32 ? 5 : 4;
+    if (kcontig) { row = e >> SH; kk = e & (KC - 1); }
+    else { row = ((e >> (SH + 4)) << 4) | (e & 15); kk = (e >> 4) & (KC - 1); }
 }
-
-// Workgroups are dispatched to the eight XCDs round-robin.  With DMRG_XCD the
-// grid (a multiple of 8) is mapped so that XCD x runs the contiguous range
-// [x*per, (x+1)*per) of the ordered work list, keeping tasks that share
-// operands under one L2; -1 for workgroups past the end.
-#ifndef DMRG_XCD
-#define DMRG_XCD 0
-#endif
-__device__ inline int task_of_block(int b, int nblk) {
-    if (!DMRG_XCD) return b;
-    const int per = nblk >> 3;
-    return (b & 7) * per + (b >> 3);
-}
-__host__ inline int grid_blocks(int n) { return DMRG_XCD ? (n + 7) / 8 * 8 : n; }
 
 // Minimum waves per SIMD each tile-kernel instantiation is compiled for
 // (caps registers at 512 / waves), chosen by measurement: FP32 tiles of three
 // or more slices fit 128 registers; narrower FP32 tiles and FP64 tiles need more.
-template <typename T, int NCT> struct Occ { static constexpr int waves = sizeof(T) == 4 ? (NCT <= 2 ? 3 : 4) : 2; };
+// k per LDS chunk.  The kernel supports 16 and 32; 16 is used: a 32-wide
+// chunk halves the chunks and barriers per MFMA, but its extra registers cost
+// a wave per SIMD, which measured slower on the 54-orbital workload.
+template <typename T, int NCT> struct ChunkK { static constexpr int kc = 16; };
+
+template <typename T, int NCT> struct Occ {
+    static constexpr int waves = sizeof(T) == 4 ? ((NCT <= 2 || ChunkK<T, NCT>::kc == 32) ? 3 : 4) : 2;
+};
 
 // The buffer table is read through the kernel-argument segment so that an
 // index known only at run time becomes a scalar load rather than a select
@@ -231,9 +226,11 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                                                                                const Contrib* __restrict__ contribs) {
     using V4 = typename Mfma<T>::v4;
     constexpr int NT = 64 * NCT;
-    constexpr int LD = Lds<T>::ld;
+    constexpr int KC = ChunkK<T, NCT>::kc;        // k per LDS chunk
+    constexpr int KS = KC / 16;                   // 16-k MFMA groups per chunk
+    constexpr int LD = Lds<T, KC>::ld;
     constexpr int AR = 16 * kRT;                  // rows of the A / X slot
-    constexpr int EA = (AR * kKC + NT - 1) / NT;  // A-slot elements per thread
+    constexpr int EA = (AR * KC + NT - 1) / NT;   // A-slot elements per thread
     __shared__ __attribute__((aligned(16))) T sA[2][AR * LD];
     __shared__ Group sG[LR ? kRecG : 1];
     __shared__ Contrib sC[LR ? kRecC : 1];
@@ -244,9 +241,8 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     const int w = tid >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
-    const int bid = task_of_block(blockIdx.x, gridDim.x);
-    if (bid < 0 || bid >= ntask) return;   // padding of the XCD-mapped grid
-    const Task tk = tasks[bid];
+    if ((int)blockIdx.x >= ntask) return;
+    const Task tk = tasks[blockIdx.x];
     const int vec = blockIdx.y;
     const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
     const int nrm = (tk.m + 15) >> 4;                // output row tiles
@@ -270,9 +266,10 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     // The B operand (this wave's 16 columns) is not shared between waves: it is
     // loaded straight into MFMA fragment registers (rb, in flight; rbc, the
     // current chunk's copy) instead of through LDS.  For an A . B chunk lane
-    // (c, g) holds B[k0 + 4g + s][c] (s = 0..3); for an identity chunk it holds
-    // operand rows k0 + row(g, v) of column c, the accumulator layout of U.
-    T ra[EA], rb[4], rbc[4];
+    // (c, g) holds B[k0 + 16q + 4g + s][c] (q < KS, s < 4); for an identity
+    // chunk it holds operand rows k0 + 16q + row(g, v) of column c, the
+    // accumulator layout of U.
+    T ra[EA], rb[4 * KS], rbc[4 * KS];
     uint32_t a_ok = 0, b_ok = 0, b_okc = 0;   // element valid
     T a_scale = 0, b_scale = 0, b_scalec = 0;
     bool a_tr = false;                        // layout of the chunk held in ra
@@ -286,13 +283,13 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
             const T* p = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
             const int ld = gr.ldx, rows = tk.m, K = gr.mu;
             const bool tr = (gr.flags & G_TRANS_X) != 0;
-            const int nel = nrm * 256;
+            const int nel = nrm * 16 * KC;
             uint32_t ok = 0;
 #pragma unroll
             for (int i = 0; i < EA; ++i) {
                 const int e = tid + i * NT;
                 int row, kk;
-                chunk_elem(e, !tr, row, kk);
+                chunk_elem<KC>(e, !tr, row, kk);
                 const int k = ch.k0 + kk;
                 const bool v = e < nel && row < rows && k < K;
                 ra[i] = ld_at(p, v ? (tr ? (uint32_t)(k * ld + row) : (uint32_t)(row * ld + k)) : 0u);
@@ -310,13 +307,13 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
             const T* q = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int lda = ct.lda, ldb = ct.ldb, rows = gr.mu, K = ct.k;
-            const int nel = ((rows + 15) >> 4) * 256;
+            const int nel = ((rows + 15) >> 4) * 16 * KC;
             uint32_t ok = 0;
 #pragma unroll
             for (int i = 0; i < EA; ++i) {
                 const int e = tid + i * NT;
                 int row, kk;
-                chunk_elem(e, !ta, row, kk);
+                chunk_elem<KC>(e, !ta, row, kk);
                 const int k = ch.k0 + kk;
                 const bool v = e < nel && row < rows && k < K;
                 ra[i] = ld_at(p, v ? (ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k)) : 0u);
@@ -326,8 +323,8 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
             ok = 0;
             const int c = tk.col0 + mycol;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = ch.k0 + 4 * lk + s;
+            for (int s = 0; s < 4 * KS; ++s) {
+                const int k = ch.k0 + 16 * (s >> 2) + 4 * lk + (s & 3);
                 const bool v = mycol < ncv && k < K;
                 rb[s] = ld_at(q, v ? (tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c)) : 0u);
                 ok |= (uint32_t)v << s;
@@ -349,8 +346,8 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
         const int c = tk.col0 + mycol;
         uint32_t ok = 0;
 #pragma unroll
-        for (int v4 = 0; v4 < 4; ++v4) {
-            const int row = ch.k0 + Mfma<T>::row(lk, v4);
+        for (int v4 = 0; v4 < 4 * KS; ++v4) {
+            const int row = ch.k0 + 16 * (v4 >> 2) + Mfma<T>::row(lk, v4 & 3);
             const bool v = mycol < ncv && row < gr.mu;
             if (ida && idb)   // a_off: diagonal offset of the identity
                 rb[v4] = ((int64_t)row + ct.a_off == c) ? T(1) : T(0);
@@ -365,16 +362,16 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     auto store = [&](const Chunk& ch, int b) {
         if (ch.kind != CH_XU) {   // B fragments of this chunk: masked and scaled copy
 #pragma unroll
-            for (int s = 0; s < 4; ++s) rbc[s] = ((b_ok >> s) & 1) ? b_scale * rb[s] : T(0);
+            for (int s = 0; s < 4 * KS; ++s) rbc[s] = ((b_ok >> s) & 1) ? b_scale * rb[s] : T(0);
         }
         if (ch.kind != CH_ID) {
-            const int nel = ((a_rows + 15) >> 4) * 256;
+            const int nel = ((a_rows + 15) >> 4) * 16 * KC;
 #pragma unroll
             for (int i = 0; i < EA; ++i) {
                 const int e = tid + i * NT;
                 if (e < nel) {
                     int row, kk;
-                    chunk_elem(e, !a_tr, row, kk);
+                    chunk_elem<KC>(e, !a_tr, row, kk);
                     sA[b][row * LD + (ch.kind == CH_XU ? xu_pos<T>(kk) : kk)] =
                         ((a_ok >> i) & 1) ? a_scale * ra[i] : T(0);
                 }
@@ -389,7 +386,7 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     while (cur.g >= 0) {
         store(cur, buf);
         __syncthreads();   // chunk cur complete in LDS; the buffer written next is free
-        const Chunk nx = next_chunk(R, cur, tk.g1);
+        const Chunk nx = next_chunk<KC>(R, cur, tk.g1);
         if (nx.g >= 0) load(nx);   // in flight during the MFMAs below
         if (cur.g != gcur) {
 #pragma unroll
@@ -407,10 +404,13 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
 #pragma unroll
             for (int i = 0; i < kRT; ++i) {
                 if (i >= nru) continue;
-                T af[4];
-                lds_read4(A + (16 * i + lr) * LD + 4 * lk, af);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(af[s], bf[s], U[i]);
+                for (int q = 0; q < KS; ++q) {
+                    T af[4];
+                    lds_read4(A + (16 * i + lr) * LD + 16 * q + 4 * lk, af);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(af[s], bf[4 * q + s], U[i]);
+                }
                 if (i & 1) __builtin_amdgcn_sched_barrier(0);
             }
         } else if (cur.kind == CH_XU) {
@@ -419,6 +419,7 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                 for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
                 xi = 0;
             }
+            // the chunk covers U row tiles j .. j + KS - 1
             tile_switch(cur.k0 >> 4, [&](auto J) {
                 constexpr int j = decltype(J)::value;
 #pragma unroll
@@ -428,6 +429,11 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                     lds_read4(A + (16 * i + lr) * LD + 4 * lk, xf);
 #pragma unroll
                     for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[s], U[j][s], acc[i]);
+                    if constexpr (KS == 2 && j + 1 < kRT) {
+                        lds_read4(A + (16 * i + lr) * LD + 16 + 4 * lk, xf);
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[s], U[j + 1][s], acc[i]);
+                    }
                     if (i & 1) __builtin_amdgcn_sched_barrier(0);
                 }
             });
@@ -436,6 +442,10 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                 constexpr int j = decltype(J)::value;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) U[j][v] += rbc[v];
+                if constexpr (KS == 2 && j + 1 < kRT) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) U[j + 1][v] += rbc[4 + v];
+                }
             });
         }
         buf ^= 1;
@@ -486,9 +496,8 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
     __shared__ Contrib sC[LR ? 4 : 1][LR ? kRecC : 1];
     (void)Bargs;
     const int wv = threadIdx.x >> 6;
-    const int bid = task_of_block(blockIdx.x, gridDim.x);
-    const int ti = bid * 4 + wv;
-    if (bid < 0 || ti >= ntask) return;   // also the padding of the XCD-mapped grid
+    const int ti = blockIdx.x * 4 + wv;
+    if (ti >= ntask) return;
     const int lane = threadIdx.x & 63;
     const int lr = lane & 15;
     const int lk = lane >> 4;
@@ -664,7 +673,7 @@ template <typename T, bool LR>
 static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
                           int nvec, hipStream_t s) {
     if (cls >= kNumTileClass) {   // wave classes: four tasks per workgroup
-        const dim3 grid(grid_blocks((ntask + 3) / 4), nvec), block(256);
+        const dim3 grid((ntask + 3) / 4, nvec), block(256);
         switch (cls - kNumTileClass) {
             case 0: hipLaunchKernelGGL((wave_kernel<T, 1, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
             case 1: hipLaunchKernelGGL((wave_kernel<T, 1, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
@@ -674,7 +683,7 @@ static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, con
         }
         return (int)hipGetLastError();
     }
-    const dim3 grid(grid_blocks(ntask), nvec), block(64 * (cls + 1));
+    const dim3 grid(ntask, nvec), block(64 * (cls + 1));
     switch (cls) {
         case 0: hipLaunchKernelGGL((tile_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
         case 1: hipLaunchKernelGGL((tile_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
@@ -705,28 +714,50 @@ int launch_chain_f32(int cls, bool lds_records, const Task* t, int ntask, const 
     return launch_chain<float>(cls, lds_records, t, ntask, g, c, b, nvec, stream);
 }
 
+// One workgroup per split tile.  Each thread owns up to kRedPer elements of
+// the tile (stride kRedThreads, so every load of one slot is coalesced) and
+// keeps their sums in registers while it walks the slots.  The loads of a
+// slot are unconditional (indices past the tile are clamped to its last
+// element and their sums discarded), so they are all in flight together;
+// each element is still summed in slot order.
+constexpr int kRedThreads = 512;
+constexpr int kRedPer = (kMaxRows * kMaxCols + kRedThreads - 1) / kRedThreads;
+
 template <typename T>
-__global__ __launch_bounds__(256) void reduce_kernel(const Reduce* __restrict__ red, Bases<T> b) {
+__global__ __launch_bounds__(kRedThreads) void reduce_kernel(const Reduce* __restrict__ red, Bases<T> b) {
     const Reduce r = red[blockIdx.x];
     const int vec = blockIdx.y;
     const int cbuf = r.cbuf & 15;
     const bool accum = (r.cbuf >> 8) & 1;
     const T* P = b.p[kPartialBuf] + r.poff + (int64_t)vec * b.vstride[kPartialBuf];
     T* Cp = b.p[cbuf] + r.c_off + (int64_t)vec * b.vstride[cbuf];
-    const int64_t slot = (int64_t)r.m * r.ncol;
-    for (int e = threadIdx.x; e < slot; e += blockDim.x) {
+    const int slot = r.m * r.ncol;   // <= kMaxRows * kMaxCols (checked on the host)
+    const int tid = threadIdx.x;
+    T s[kRedPer];
+#pragma unroll
+    for (int i = 0; i < kRedPer; ++i) s[i] = 0;
+    for (int q = 0; q < r.nslot; ++q) {
+        const T* Pq = P + (int64_t)q * slot;
+        T v[kRedPer];
+#pragma unroll
+        for (int i = 0; i < kRedPer; ++i) v[i] = Pq[min(tid + i * kRedThreads, slot - 1)];
+#pragma unroll
+        for (int i = 0; i < kRedPer; ++i) s[i] += v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kRedPer; ++i) {
+        const int e = tid + i * kRedThreads;
+        if (e >= slot) continue;
         const int row = e / r.ncol, j = e - row * r.ncol;
-        T s = 0;
-        for (int q = 0; q < r.nslot; ++q) s += P[q * slot + e];
         T* d = Cp + (int64_t)row * r.ldc + r.col0 + j;
-        *d = accum ? *d + s : s;
+        *d = accum ? *d + s[i] : s[i];
     }
 }
 
 template <typename T>
 static int launch_reduce(const Reduce* r, int nred, const Bases<T>& b, int nvec, void* stream) {
     if (nred <= 0) return 0;
-    hipLaunchKernelGGL(reduce_kernel<T>, dim3(nred, nvec), dim3(256), 0, (hipStream_t)stream, r, b);
+    hipLaunchKernelGGL(reduce_kernel<T>, dim3(nred, nvec), dim3(kRedThreads), 0, (hipStream_t)stream, r, b);
     return (int)hipGetLastError();
 }
 int launch_reduce_f64(const Reduce* r, int nred, const Bases<double>& b, int nvec, void* stream) {

@@ -44,7 +44,7 @@ struct Task {          // one output tile: rows 0..m-1, columns col0..col0+ncol-
     int32_t col0, ncol;
     int32_t g0, g1;    // group range
     int32_t cbuf;      // buffer id of C (bits 0-3) | accumulate << 8 | tile-local columns << 9
-    int32_t key;       // locality key (host-side task ordering only)
+    int32_t pad;
 };
 
 struct Group {
