@@ -106,7 +106,6 @@ __device__ inline T ld_at(const T* p, uint32_t off) {
 //   kind 1: X . U over U rows k0..k0+15 of group g;  g < 0: none.
 // X . U chunks come last in their group.
 enum { CH_AB = 0, CH_XU = 1, CH_ID = 2 };
-struct Chunk { int g, c, k0, kind; };
 
 // Group / contribution records of a task.  LR = false: straight from global
 // memory (scalar loads).  LR = true: the task's records were copied to LDS
@@ -129,9 +128,6 @@ template <> struct Recs<false> {
     const Contrib* __restrict__ C;
     __device__ Group group(int g) const { return G[g]; }
     __device__ Contrib contrib(int c) const { return C[c]; }
-    __device__ int cflags(int c) const { return C[c].flags; }
-    __device__ int ck(int c) const { return C[c].k; }
-    __device__ int gmu(int g) const { return G[g].mu; }
 };
 template <> struct Recs<true> {
     const Group* sg;
@@ -139,9 +135,6 @@ template <> struct Recs<true> {
     int g0, cb;
     __device__ Group group(int g) const { return lds_uniform(sg + (g - g0)); }
     __device__ Contrib contrib(int c) const { return lds_uniform(sc + (c - cb)); }
-    __device__ int cflags(int c) const { return __builtin_amdgcn_readfirstlane(sc[c - cb].flags); }
-    __device__ int ck(int c) const { return __builtin_amdgcn_readfirstlane(sc[c - cb].k); }
-    __device__ int gmu(int g) const { return __builtin_amdgcn_readfirstlane(sg[g - g0].mu); }
 };
 
 // copies the records of groups g0..g1-1 and of their (contiguous)
@@ -161,29 +154,73 @@ __device__ inline int stage_records(const Group* __restrict__ groups, const Cont
     return cb;
 }
 
-template <class RC>
-__device__ inline Chunk first_chunk(const RC& R, int g, int g1) {
-    for (; g < g1; ++g) {
-        const Group gr = R.group(g);
-        if (gr.c1 > gr.c0) return Chunk{g, gr.c0, 0, is_identity(R.cflags(gr.c0)) ? CH_ID : CH_AB};
-        if (gr.flags & G_HAS_X) return Chunk{g, 0, 0, CH_XU};
-    }
-    return Chunk{-1, 0, 0, 0};
+// Position of the chunk walk over a task's groups and contributions, with
+// the fields of the current group and contribution held in scalar
+// registers: advancing within a contribution (or within the X . U pass of a
+// group) reads no memory, so records are read only at boundaries.
+template <typename T>
+struct Cursor {
+    int g, c, k0, kind;        // g < 0: no chunk
+    int mu, gflags, ldx, c1;   // group g
+    int64_t x_off;
+    T x_coef, xid;
+    int64_t a_off, b_off;      // contribution c
+    T alpha;
+    int lda, ldb, k, cflags;
+};
+
+template <typename T, class RC>
+__device__ inline void cursor_contrib(const RC& R, Cursor<T>& q, int c) {
+    const Contrib ct = R.contrib(c);
+    q.c = c;
+    q.a_off = ct.a_off;
+    q.b_off = ct.b_off;
+    q.alpha = (T)ct.alpha;
+    q.lda = ct.lda;
+    q.ldb = ct.ldb;
+    q.k = ct.k;
+    q.cflags = ct.flags;
+    q.k0 = 0;
+    q.kind = is_identity(ct.flags) ? CH_ID : CH_AB;
 }
 
-template <int KC, class RC>
-__device__ inline Chunk next_chunk(const RC& R, Chunk ch, int g1) {
-    const Group gr = R.group(ch.g);
-    if (ch.kind == CH_XU) {
-        if (ch.k0 + KC < gr.mu) return Chunk{ch.g, 0, ch.k0 + KC, CH_XU};
-    } else {
-        const int extent = ch.kind == CH_AB ? R.ck(ch.c) : gr.mu;
-        if (ch.k0 + KC < extent) return Chunk{ch.g, ch.c, ch.k0 + KC, ch.kind};
-        if (ch.c + 1 < gr.c1)
-            return Chunk{ch.g, ch.c + 1, 0, is_identity(R.cflags(ch.c + 1)) ? CH_ID : CH_AB};
-        if (gr.flags & G_HAS_X) return Chunk{ch.g, 0, 0, CH_XU};
+// the first chunk of the first group >= g (of g < g1) that has one
+template <typename T, class RC>
+__device__ inline void cursor_group(const RC& R, Cursor<T>& q, int g, int g1) {
+    for (; g < g1; ++g) {
+        const Group gr = R.group(g);
+        q.g = g;
+        q.mu = gr.mu;
+        q.gflags = gr.flags;
+        q.ldx = gr.ldx;
+        q.c1 = gr.c1;
+        q.x_off = gr.x_off;
+        q.x_coef = (T)gr.x_coef;
+        q.xid = (T)gr.xid_coef;
+        if (gr.c1 > gr.c0) {
+            cursor_contrib(R, q, gr.c0);
+            return;
+        }
+        if (gr.flags & G_HAS_X) {
+            q.k0 = 0;
+            q.kind = CH_XU;
+            return;
+        }
     }
-    return first_chunk(R, ch.g + 1, g1);
+    q.g = -1;
+}
+
+template <int KC, typename T, class RC>
+__device__ inline void cursor_next(const RC& R, Cursor<T>& q, int g1) {
+    if (q.kind == CH_XU) {
+        if (q.k0 + KC < q.mu) { q.k0 += KC; return; }
+    } else {
+        const int extent = q.kind == CH_AB ? q.k : q.mu;
+        if (q.k0 + KC < extent) { q.k0 += KC; return; }
+        if (q.c + 1 < q.c1) { cursor_contrib(R, q, q.c + 1); return; }
+        if (q.gflags & G_HAS_X) { q.k0 = 0; q.kind = CH_XU; return; }
+    }
+    cursor_group(R, q, q.g + 1, g1);
 }
 
 // Element e of a KC-wide chunk slot (KC = 16 or 32).  kcontig: KC consecutive
@@ -204,8 +241,11 @@ __device__ inline void chunk_elem(int e, bool kcontig, int& row, int& kk) {
 // a wave per SIMD, which measured slower on the 54-orbital workload.
 template <typename T, int NCT> struct ChunkK { static constexpr int kc = 16; };
 
+#ifndef DMRG_OCC3_MAX
+#define DMRG_OCC3_MAX 3
+#endif
 template <typename T, int NCT> struct Occ {
-    static constexpr int waves = sizeof(T) == 4 ? ((NCT <= 2 || ChunkK<T, NCT>::kc == 32) ? 3 : 4) : 2;
+    static constexpr int waves = sizeof(T) == 4 ? ((NCT <= DMRG_OCC3_MAX || ChunkK<T, NCT>::kc == 32) ? 3 : 4) : 2;
 };
 
 // The buffer table is read through the kernel-argument segment so that an
@@ -277,12 +317,11 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
     static_assert(EA <= 32, "mask width");
 
     // global -> registers: the operands of chunk ch
-    auto load = [&](const Chunk& ch) {
-        const Group gr = R.group(ch.g);
+    auto load = [&](const Cursor<T>& ch) {
         if (ch.kind == CH_XU) {
-            const T* p = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
-            const int ld = gr.ldx, rows = tk.m, K = gr.mu;
-            const bool tr = (gr.flags & G_TRANS_X) != 0;
+            const T* p = base_ptr<T>(ch.gflags & 7, vec) + ch.x_off;
+            const int ld = ch.ldx, rows = tk.m, K = ch.mu;
+            const bool tr = (ch.gflags & G_TRANS_X) != 0;
             const int nel = nrm * 16 * KC;
             uint32_t ok = 0;
 #pragma unroll
@@ -296,17 +335,16 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                 ok |= (uint32_t)v << i;
             }
             a_ok = ok;
-            a_scale = (T)gr.x_coef;
+            a_scale = ch.x_coef;
             a_tr = tr;
             a_rows = rows;
             return;
         }
-        const Contrib ct = R.contrib(ch.c);
         if (ch.kind == CH_AB) {
-            const T* p = base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
-            const T* q = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
-            const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
-            const int lda = ct.lda, ldb = ct.ldb, rows = gr.mu, K = ct.k;
+            const T* p = base_ptr<T>(ch.cflags & 7, vec) + ch.a_off;
+            const T* q = base_ptr<T>((ch.cflags >> 3) & 7, vec) + ch.b_off;
+            const bool ta = (ch.cflags & F_TRANS_A) != 0, tb = (ch.cflags & F_TRANS_B) != 0;
+            const int lda = ch.lda, ldb = ch.ldb, rows = ch.mu, K = ch.k;
             const int nel = ((rows + 15) >> 4) * 16 * KC;
             uint32_t ok = 0;
 #pragma unroll
@@ -330,7 +368,7 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
                 ok |= (uint32_t)v << s;
             }
             b_ok = ok;
-            a_scale = (T)ct.alpha;
+            a_scale = ch.alpha;
             b_scale = T(1);
             a_tr = ta;
             a_rows = rows;
@@ -338,28 +376,28 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
         }
         // identity contribution: rows k0 + row(g, v) of alpha * operand (or of
         // alpha * I shifted by a_off), this lane's column
-        const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
-        const T* p = ida ? base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off
-                         : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
-        const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
-        const int ld = ida ? ct.ldb : ct.lda;
+        const bool ida = (ch.cflags & F_ID_A) != 0, idb = (ch.cflags & F_ID_B) != 0;
+        const T* p = ida ? base_ptr<T>((ch.cflags >> 3) & 7, vec) + ch.b_off
+                         : base_ptr<T>(ch.cflags & 7, vec) + ch.a_off;
+        const bool tp = ida ? (ch.cflags & F_TRANS_B) != 0 : (ch.cflags & F_TRANS_A) != 0;
+        const int ld = ida ? ch.ldb : ch.lda;
         const int c = tk.col0 + mycol;
         uint32_t ok = 0;
 #pragma unroll
         for (int v4 = 0; v4 < 4 * KS; ++v4) {
             const int row = ch.k0 + 16 * (v4 >> 2) + Mfma<T>::row(lk, v4 & 3);
-            const bool v = mycol < ncv && row < gr.mu;
+            const bool v = mycol < ncv && row < ch.mu;
             if (ida && idb)   // a_off: diagonal offset of the identity
-                rb[v4] = ((int64_t)row + ct.a_off == c) ? T(1) : T(0);
+                rb[v4] = ((int64_t)row + ch.a_off == c) ? T(1) : T(0);
             else
                 rb[v4] = ld_at(p, v ? (tp ? (uint32_t)(c * ld + row) : (uint32_t)(row * ld + c)) : 0u);
             ok |= (uint32_t)v << v4;
         }
         b_ok = ok;
-        b_scale = (T)ct.alpha;
+        b_scale = ch.alpha;
     };
     // registers -> LDS buffer b (masking and scaling here, after the loads landed)
-    auto store = [&](const Chunk& ch, int b) {
+    auto store = [&](const auto& ch, int b) {
         if (ch.kind != CH_XU) {   // B fragments of this chunk: masked and scaled copy
 #pragma unroll
             for (int s = 0; s < 4 * KS; ++s) rbc[s] = ((b_ok >> s) & 1) ? b_scale * rb[s] : T(0);
@@ -379,26 +417,30 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
         }
     };
 
-    Chunk cur = first_chunk(R, tk.g0, tk.g1);
-    if (cur.g >= 0) load(cur);
+    // q: the chunk whose operands are loaded next; cur: the chunk computed
+    struct Cur { int g, kind, k0, mu; T xid; };
+    Cursor<T> q;
+    cursor_group(R, q, tk.g0, tk.g1);
+    if (q.g >= 0) load(q);
+    Cur cur{q.g, q.kind, q.k0, q.mu, q.xid};
     int buf = 0, gcur = -1;
     T xi = 0;   // identity-X coefficient of group gcur still to be applied (0 once applied)
     while (cur.g >= 0) {
         store(cur, buf);
         __syncthreads();   // chunk cur complete in LDS; the buffer written next is free
-        const Chunk nx = next_chunk<KC>(R, cur, tk.g1);
-        if (nx.g >= 0) load(nx);   // in flight during the MFMAs below
+        cursor_next<KC>(R, q, tk.g1);
+        if (q.g >= 0) load(q);   // in flight during the MFMAs below
         if (cur.g != gcur) {
 #pragma unroll
             for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
 #pragma unroll
             for (int i = 0; i < kRT; ++i) U[i] = V4{0, 0, 0, 0};
             gcur = cur.g;
-            xi = (T)R.group(gcur).xid_coef;
+            xi = cur.xid;
         }
         const T* A = sA[buf];
         if (cur.kind == CH_AB) {
-            const int nru = (R.gmu(cur.g) + 15) >> 4;
+            const int nru = (cur.mu + 15) >> 4;
             const T* bf = rbc;
             // row tiles in pairs: fragments of at most two tiles live at once
 #pragma unroll
@@ -449,7 +491,7 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
             });
         }
         buf ^= 1;
-        cur = nx;
+        cur = Cur{q.g, q.kind, q.k0, q.mu, q.xid};
     }
 #pragma unroll
     for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
