@@ -64,6 +64,22 @@ __device__ inline void lds_read4(const T* p, T (&f)[4]) {
     }
 }
 
+// Four consecutive elements at a 32-bit element offset of a uniform base
+// (element alignment only: the loads are 16-byte vector loads, which gfx950
+// performs at any 4-byte alignment).
+typedef float F4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef double D2u __attribute__((ext_vector_type(2), aligned(8)));
+__device__ inline void ld4_at(const float* p, uint32_t off, float (&r)[4]) {
+    const F4u v = *reinterpret_cast<const F4u*>(reinterpret_cast<const char*>(p) + off * 4u);
+    r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+}
+__device__ inline void ld4_at(const double* p, uint32_t off, double (&r)[4]) {
+    const char* b = reinterpret_cast<const char*>(p) + off * 8u;
+    const D2u v = *reinterpret_cast<const D2u*>(b);
+    const D2u w = *reinterpret_cast<const D2u*>(b + 16);
+    r[0] = v.x; r[1] = v.y; r[2] = w.x; r[3] = w.y;
+}
+
 __device__ inline bool is_identity(int flags) { return (flags & (F_ID_A | F_ID_B)) != 0; }
 
 // Calls f(std::integral_constant<int, j>) for a run-time j in [0, 6): one
@@ -360,12 +376,23 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
             a_ok = ok;
             ok = 0;
             const int c = tk.col0 + mycol;
+            if (KS == 1 && tb && ch.k0 + KC <= K) {
+                // a full chunk of a transposed operand: the lane's four k are
+                // consecutive in the operand row, one vector load
+                const bool v = mycol < ncv;
+                T r4[4];
+                ld4_at(q, v ? (uint32_t)(c * ldb + ch.k0 + 4 * lk) : 0u, r4);
 #pragma unroll
-            for (int s = 0; s < 4 * KS; ++s) {
-                const int k = ch.k0 + 16 * (s >> 2) + 4 * lk + (s & 3);
-                const bool v = mycol < ncv && k < K;
-                rb[s] = ld_at(q, v ? (tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c)) : 0u);
-                ok |= (uint32_t)v << s;
+                for (int s = 0; s < 4; ++s) rb[s] = r4[s];
+                ok = v ? 0xfu : 0u;
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4 * KS; ++s) {
+                    const int k = ch.k0 + 16 * (s >> 2) + 4 * lk + (s & 3);
+                    const bool v = mycol < ncv && k < K;
+                    rb[s] = ld_at(q, v ? (tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c)) : 0u);
+                    ok |= (uint32_t)v << s;
+                }
             }
             b_ok = ok;
             a_scale = ch.alpha;
