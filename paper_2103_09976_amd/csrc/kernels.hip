@@ -544,6 +544,233 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
 }
 
 // ---------------------------------------------------------------------------
+// slice_kernel: the tasks of tile_kernel (one workgroup per output tile of
+// <= 80 rows x 16*NCT columns), but every wave computes its 16-column slice on
+// its own.  MFMA fragments are loaded straight from global memory into
+// operand registers -- one 16-byte vector load per lane and row tile where
+// the operand's layout puts the lane's four k next to each other -- so the
+// chunk loop has no LDS staging and no barrier.  The waves of a tile share a
+// workgroup (and a CU), so the A and X rows they all read come from L1 after
+// the first wave's miss.
+//
+// Per group: U = sum_c alpha_c A_c B_c over 16-k chunks; then U's rows past
+// mu (products of clamped A rows) are zeroed, the identity term xid * U is
+// added, U is scaled by x_coef and C += X . U runs over U's row tiles.
+// ---------------------------------------------------------------------------
+#ifndef DMRG_SLICE_OCC32
+#define DMRG_SLICE_OCC32 4
+#endif
+template <typename T> struct SliceOcc { static constexpr int waves = sizeof(T) == 4 ? DMRG_SLICE_OCC32 : 2; };
+
+template <typename T, int NCT, bool LR>
+__global__ __launch_bounds__(64 * NCT, (SliceOcc<T>::waves)) void slice_kernel(Bases<T> Bargs,
+                                                                             const Task* __restrict__ tasks,
+                                                                             int ntask,
+                                                                             const Group* __restrict__ groups,
+                                                                             const Contrib* __restrict__ contribs) {
+    using V4 = typename Mfma<T>::v4;
+    constexpr int NT = 64 * NCT;
+    __shared__ Group sG[LR ? kRecG : 1];
+    __shared__ Contrib sC[LR ? kRecC : 1];
+    (void)Bargs;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int lr0 = lane & 15;
+    const int lk0 = lane >> 4;
+    if ((int)blockIdx.x >= ntask) return;
+    const Task tk = tasks[blockIdx.x];
+    const int vec = blockIdx.y;
+    const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
+    const int nrm = (tk.m + 15) >> 4;                // output row tiles
+    Recs<LR> R;
+    if constexpr (LR) {
+        const int cb = stage_records(groups, contribs, tk.g0, tk.g1, sG, sC, tid, NT);
+        __syncthreads();
+        R = Recs<true>{sG, sC, tk.g0, cb};
+    } else {
+        R = Recs<false>{groups, contribs};
+    }
+
+    V4 acc[kRT];
+#pragma unroll
+    for (int i = 0; i < kRT; ++i) acc[i] = V4{0, 0, 0, 0};
+    // The lane coordinates are passed through an empty asm inside each loop,
+    // so that the compiler recomputes the cheap per-lane bounds there instead
+    // of hoisting dozens of lane masks out of the loops (which spilled).
+    auto opaque = [](int x) { asm volatile("" : "+v"(x)); return x; };
+
+    for (int g = tk.g0; g < tk.g1; ++g) {
+        const Group gr = R.group(g);
+        const int mu = gr.mu;
+        const int nru = (mu + 15) >> 4;   // row tiles of U
+        V4 U[kRT];
+#pragma unroll
+        for (int i = 0; i < kRT; ++i) U[i] = V4{0, 0, 0, 0};
+        for (int c = gr.c0; c < gr.c1; ++c) {
+            const Contrib ct = R.contrib(c);
+            const T alpha = (T)ct.alpha;
+            if (is_identity(ct.flags)) {
+                // U rows row(g, v) of tile i += alpha * operand (or alpha * shifted I), this lane's column
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                const int gcol = tk.col0 + 16 * w + lr;
+                const bool colok = 16 * w + lr < ncv;
+                const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
+                const T* P = ida ? base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off
+                                 : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
+                const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
+                const int ld = ida ? ct.ldb : ct.lda;
+#pragma unroll
+                for (int i = 0; i < kRT; ++i) {
+                    if (i >= nru) continue;
+                    T x[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * i + Mfma<T>::row(lk, v);
+                        const bool ok = row < mu && colok;
+                        if (ida && idb)   // a_off: diagonal offset of the identity (within the block)
+                            x[v] = (row + (int)ct.a_off == gcol) ? T(1) : T(0);
+                        else
+                            x[v] = ld_at(P, ok ? (tp ? (uint32_t)(gcol * ld + row) : (uint32_t)(row * ld + gcol)) : 0u);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * i + Mfma<T>::row(lk, v);
+                        U[i][v] += (row < mu && colok) ? alpha * x[v] : T(0);
+                    }
+                }
+                continue;
+            }
+            const T* Ap = base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
+            const T* Bp = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
+            const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
+            const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                // all fragment loads of the chunk first (clamped when out of
+                // range), then one wait and the MFMAs.  Lane (r, g) takes
+                // k = k0 + 4g + s: rows 16i + r of A, column gcol of B.
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                const int gcol = tk.col0 + 16 * w + lr;
+                const bool colok = 16 * w + lr < ncv;
+                const bool full = k0 + 16 <= K;
+                T fa[kRT][4], fb[4];
+#pragma unroll
+                for (int i = 0; i < kRT; ++i) {
+                    if (i >= nru) continue;
+                    const int row = 16 * i + lr;
+                    const bool rok = row < mu;
+                    if (!ta && full) {
+                        ld4_at(Ap, rok ? (uint32_t)(row * lda + k0 + 4 * lk) : 0u, fa[i]);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int k = k0 + 4 * lk + s;
+                            const bool ok = rok && k < K;
+                            fa[i][s] = ld_at(Ap, ok ? (ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k)) : 0u);
+                        }
+                    }
+                }
+                if (tb && full) {
+                    ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + k0 + 4 * lk) : 0u, fb);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = k0 + 4 * lk + s;
+                        const bool ok = colok && k < K;
+                        fb[s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gcol * ldb + k) : (uint32_t)(k * ldb + gcol)) : 0u);
+                    }
+                }
+                // k past K or a column past the tile: zero B (A's clamped rows
+                // only reach U rows past mu, zeroed below)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) fb[s] = (colok && k0 + 4 * lk + s < K) ? alpha * fb[s] : T(0);
+#pragma unroll
+                for (int i = 0; i < kRT; ++i) {
+                    if (i >= nru) continue;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(fa[i][s], fb[s], U[i]);
+                }
+            }
+        }
+        {
+            const int lk = opaque(lk0);
+#pragma unroll
+            for (int i = 0; i < kRT; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (16 * i + Mfma<T>::row(lk, v) >= mu) U[i][v] = T(0);
+        }
+        if (gr.xid_coef != 0.0) {
+            const T xi = (T)gr.xid_coef;
+#pragma unroll
+            for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
+        }
+        if (gr.flags & G_HAS_X) {
+            const T* Xp = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
+            const bool tx = (gr.flags & G_TRANS_X) != 0;
+            const T xc = (T)gr.x_coef;
+            const int ldx = gr.ldx;
+#pragma unroll
+            for (int i = 0; i < kRT; ++i) U[i] *= xc;
+            // X . U over U's row tiles q: lane (r, g) takes X rows 16i + r,
+            // k = 16q + row(g, s), the rows U's accumulator holds in the lane
+#pragma unroll
+            for (int q = 0; q < kRT; ++q) {
+                if (q >= nru) continue;
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                const bool full = 16 * q + 16 <= mu;
+                T xf[kRT][4];
+#pragma unroll
+                for (int i = 0; i < kRT; ++i) {
+                    if (i >= nrm) continue;
+                    const int row = 16 * i + lr;
+                    const bool rok = row < tk.m;
+                    if (Mfma<T>::row(1, 0) == 4 && !tx && full) {
+                        ld4_at(Xp, rok ? (uint32_t)(row * ldx + 16 * q + 4 * lk) : 0u, xf[i]);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int k = 16 * q + Mfma<T>::row(lk, s);
+                            const bool ok = rok && k < mu;
+                            xf[i][s] = ld_at(Xp, ok ? (tx ? (uint32_t)(k * ldx + row) : (uint32_t)(row * ldx + k)) : 0u);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kRT; ++i) {
+                    if (i >= nrm) continue;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[i][s], U[q][s], acc[i]);
+                }
+                __builtin_amdgcn_sched_barrier(0);   // one row tile of U at a time
+            }
+        }
+    }
+
+    const int cbuf = tk.cbuf & 15;
+    const bool accum = (tk.cbuf >> 8) & 1;
+    const bool local = (tk.cbuf >> 9) & 1;   // partial slot: columns from 0
+    T* Cp = const_cast<T*>(base_ptr<T>(cbuf, vec)) + tk.c_off + (local ? 0 : tk.col0);
+    const int lk = lk0;
+    const int mycol = 16 * w + lr0;   // tile-local column of this lane
+    if (mycol < ncv) {
+#pragma unroll
+        for (int i = 0; i < kRT; ++i) {
+            if (i >= nrm) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * i + Mfma<T>::row(lk, v);
+                if (row < tk.m) {
+                    T* d = Cp + (uint32_t)(row * tk.ldc + mycol);
+                    *d = accum ? *d + acc[i][v] : acc[i][v];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // wave_kernel: tiles of at most 16*RT rows (and U rows) x 16*CT columns.  One
 // wave per task, four independent tasks per workgroup, no LDS and no
 // barrier: MFMA fragments come straight from global memory and the
@@ -738,6 +965,9 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
         }
 }
 
+#ifndef DMRG_SLICE
+#define DMRG_SLICE 1
+#endif
 template <typename T, bool LR>
 static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
                           int nvec, hipStream_t s) {
@@ -753,6 +983,18 @@ static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, con
         return (int)hipGetLastError();
     }
     const dim3 grid(ntask, nvec), block(64 * (cls + 1));
+    if (DMRG_SLICE) {
+        switch (cls) {
+            case 0: hipLaunchKernelGGL((slice_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 1: hipLaunchKernelGGL((slice_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 2: hipLaunchKernelGGL((slice_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 3: hipLaunchKernelGGL((slice_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 4: hipLaunchKernelGGL((slice_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 5: hipLaunchKernelGGL((slice_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            default: return (int)hipErrorInvalidValue;
+        }
+        return (int)hipGetLastError();
+    }
     switch (cls) {
         case 0: hipLaunchKernelGGL((tile_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
         case 1: hipLaunchKernelGGL((tile_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
