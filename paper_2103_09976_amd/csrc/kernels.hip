@@ -560,35 +560,46 @@ __global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Ba
 #ifndef DMRG_SLICE_OCC32
 #define DMRG_SLICE_OCC32 4
 #endif
-template <typename T> struct SliceOcc { static constexpr int waves = sizeof(T) == 4 ? DMRG_SLICE_OCC32 : 2; };
+#ifndef DMRG_SLICE_OCC64
+#define DMRG_SLICE_OCC64 2
+#endif
+template <typename T> struct SliceOcc {
+    static constexpr int waves = sizeof(T) == 4 ? DMRG_SLICE_OCC32 : DMRG_SLICE_OCC64;
+};
+
 
 template <typename T, int NCT, bool LR>
-__global__ __launch_bounds__(64 * NCT, (SliceOcc<T>::waves)) void slice_kernel(Bases<T> Bargs,
-                                                                             const Task* __restrict__ tasks,
-                                                                             int ntask,
-                                                                             const Group* __restrict__ groups,
-                                                                             const Contrib* __restrict__ contribs) {
+__global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<T> Bargs,
+                                                                        const Task* __restrict__ tasks,
+                                                                        int ntask,
+                                                                        const Group* __restrict__ groups,
+                                                                        const Contrib* __restrict__ contribs) {
     using V4 = typename Mfma<T>::v4;
-    constexpr int NT = 64 * NCT;
-    __shared__ Group sG[LR ? kRecG : 1];
-    __shared__ Contrib sC[LR ? kRecC : 1];
+    __shared__ Group sG[LR ? 4 : 1][LR ? kRecG : 1];
+    __shared__ Contrib sC[LR ? 4 : 1][LR ? kRecC : 1];
     (void)Bargs;
 
+    // four slices per workgroup: wave wv takes unit u = 4 blockIdx.x + wv,
+    // column slice u % NCT of task u / NCT
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int w = tid >> 6;
+    const int wv = tid >> 6;
+    const int u = blockIdx.x * 4 + wv;
+    if (u >= ntask * NCT) return;
+    const int w = u % NCT;
     const int lr0 = lane & 15;
     const int lk0 = lane >> 4;
-    if ((int)blockIdx.x >= ntask) return;
-    const Task tk = tasks[blockIdx.x];
+    const Task tk = tasks[u / NCT];
     const int vec = blockIdx.y;
     const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
     const int nrm = (tk.m + 15) >> 4;                // output row tiles
     Recs<LR> R;
-    if constexpr (LR) {
-        const int cb = stage_records(groups, contribs, tk.g0, tk.g1, sG, sC, tid, NT);
-        __syncthreads();
-        R = Recs<true>{sG, sC, tk.g0, cb};
+    if constexpr (LR) {   // each wave stages its own task's records; in-order LDS within a wave
+        const int cb = stage_records(groups, contribs, tk.g0, tk.g1, sG[wv], sC[wv], lane, 64);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        R = Recs<true>{sG[wv], sC[wv], tk.g0, cb};
     } else {
         R = Recs<false>{groups, contribs};
     }
@@ -646,15 +657,13 @@ __global__ __launch_bounds__(64 * NCT, (SliceOcc<T>::waves)) void slice_kernel(B
             const T* Bp = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
-            for (int k0 = 0; k0 < K; k0 += 16) {
-                // all fragment loads of the chunk first (clamped when out of
-                // range), then one wait and the MFMAs.  Lane (r, g) takes
-                // k = k0 + 4g + s: rows 16i + r of A, column gcol of B.
+            // the fragment loads of the chunk at k0 (clamped when out of range).
+            // Lane (r, g) takes k = k0 + 4g + s: rows 16i + r of A, column gcol of B.
+            auto fetch = [&](int k0, T (&fa)[kRT][4], T (&fb)[4]) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const int gcol = tk.col0 + 16 * w + lr;
                 const bool colok = 16 * w + lr < ncv;
                 const bool full = k0 + 16 <= K;
-                T fa[kRT][4], fb[4];
 #pragma unroll
                 for (int i = 0; i < kRT; ++i) {
                     if (i >= nru) continue;
@@ -681,8 +690,13 @@ __global__ __launch_bounds__(64 * NCT, (SliceOcc<T>::waves)) void slice_kernel(B
                         fb[s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gcol * ldb + k) : (uint32_t)(k * ldb + gcol)) : 0u);
                     }
                 }
-                // k past K or a column past the tile: zero B (A's clamped rows
-                // only reach U rows past mu, zeroed below)
+            };
+            // U += alpha * A . B of the chunk at k0.  k past K or a column past
+            // the tile: B is zeroed (A's clamped rows only reach U rows past mu,
+            // zeroed below).
+            auto mmas = [&](int k0, T (&fa)[kRT][4], T (&fb)[4]) {
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                const bool colok = 16 * w + lr < ncv;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) fb[s] = (colok && k0 + 4 * lk + s < K) ? alpha * fb[s] : T(0);
 #pragma unroll
@@ -691,6 +705,11 @@ __global__ __launch_bounds__(64 * NCT, (SliceOcc<T>::waves)) void slice_kernel(B
 #pragma unroll
                     for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(fa[i][s], fb[s], U[i]);
                 }
+            };
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                T fa[kRT][4], fb[4];
+                fetch(k0, fa, fb);
+                mmas(k0, fa, fb);
             }
         }
         {
@@ -968,9 +987,19 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
 #ifndef DMRG_SLICE
 #define DMRG_SLICE 1
 #endif
+#ifndef DMRG_SLICE_WAVE
+#define DMRG_SLICE_WAVE 0
+#endif
 template <typename T, bool LR>
 static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
                           int nvec, hipStream_t s) {
+    if (cls >= kNumTileClass && DMRG_SLICE_WAVE) {   // wave classes on the slice kernel
+        const int ct = (cls - kNumTileClass) % 2 + 1;
+        const dim3 grid((ntask * ct + 3) / 4, nvec), block(256);
+        if (ct == 1) hipLaunchKernelGGL((slice_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c);
+        else hipLaunchKernelGGL((slice_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c);
+        return (int)hipGetLastError();
+    }
     if (cls >= kNumTileClass) {   // wave classes: four tasks per workgroup
         const dim3 grid((ntask + 3) / 4, nvec), block(256);
         switch (cls - kNumTileClass) {
@@ -982,8 +1011,8 @@ static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, con
         }
         return (int)hipGetLastError();
     }
-    const dim3 grid(ntask, nvec), block(64 * (cls + 1));
-    if (DMRG_SLICE) {
+    if (DMRG_SLICE) {   // four column slices per workgroup
+        const dim3 grid((ntask * (cls + 1) + 3) / 4, nvec), block(256);
         switch (cls) {
             case 0: hipLaunchKernelGGL((slice_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
             case 1: hipLaunchKernelGGL((slice_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
@@ -995,6 +1024,7 @@ static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, con
         }
         return (int)hipGetLastError();
     }
+    const dim3 grid(ntask, nvec), block(64 * (cls + 1));
     switch (cls) {
         case 0: hipLaunchKernelGGL((tile_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
         case 1: hipLaunchKernelGGL((tile_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
