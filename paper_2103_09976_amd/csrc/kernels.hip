@@ -1,18 +1,15 @@
 // HIP kernels (gfx950) of the DMRG library.
 //
-// tile_kernel: the grouped, output-stationary sector-GEMM engine described
-// in kernels.hpp.  A workgroup of NCT waves owns one output tile of up to 80
-// rows x 16*NCT columns; wave w owns the 16-column slice w of both the tile
-// and every group intermediate U.  Per group, U (mu x 16 per wave) is
-// accumulated in MFMA registers over the contributions and then used
-// directly as the B operand of X . U, so U never leaves the registers.  The
-// operands shared by all waves (the A_c and X rows) and the B_c columns of
-// the tile are staged through double-buffered LDS in chunks of 16 k with
-// coalesced global loads; the loads of the next chunk are in flight while
-// the MFMAs of the current one run.  MFMA 16x16x4 in f64 or f32.
+// slice_kernel: the grouped, output-stationary sector-GEMM engine described
+// in kernels.hpp, for output tiles of up to 80 rows x 16*NCT columns.  Every
+// wave computes one 16-column slice of a tile on its own: per group, U
+// (mu x 16) is accumulated in MFMA registers over the contributions and used
+// directly as the B operand of X . U, so U never leaves the registers; the
+// MFMA fragments of A_c, B_c and X come straight from global memory.
+// wave_kernel: the same for tiles of at most 32 x 32.  MFMA 16x16x4 in f64
+// or f32.
 #include <hip/hip_runtime.h>
 #include <cmath>
-#include <type_traits>
 #include "kernels.hpp"
 
 namespace dmrgk {
@@ -38,31 +35,6 @@ template <> struct Mfma<float> {
 };
 
 constexpr int kRT = kMaxRows / 16;   // row tiles of a task
-constexpr int kKC = 16;              // k per LDS chunk
-
-// LDS row stride (elements) for a chunk of KC k: 16-byte aligned rows whose
-// 16-byte fragment reads by 16 consecutive rows fall on distinct banks.
-template <typename T, int KC> struct Lds { static constexpr int ld = sizeof(T) == 4 ? KC + 4 : KC + 2; };
-
-// Within a chunk, MFMA step s takes k = 4g + s from lane group g (g = l/16):
-// the four k of a lane are contiguous in an LDS row, read as one fragment.
-// For X . U the B operand is U's accumulator, whose lane group g holds rows
-// row(g, s); X is therefore stored with k at position pos(k) such that
-// position 4g + s holds k = row(g, s) (the identity for f32).
-template <typename T>
-__device__ inline int xu_pos(int kk) { return Mfma<T>::row(1, 0) == 4 ? kk : 4 * (kk & 3) + (kk >> 2); }
-
-template <typename T>
-__device__ inline void lds_read4(const T* p, T (&f)[4]) {
-    if constexpr (sizeof(T) == 4) {
-        const float4 v = *reinterpret_cast<const float4*>(p);
-        f[0] = v.x; f[1] = v.y; f[2] = v.z; f[3] = v.w;
-    } else {
-        const double2 a = *reinterpret_cast<const double2*>(p);
-        const double2 b = *reinterpret_cast<const double2*>(p + 2);
-        f[0] = a.x; f[1] = a.y; f[2] = b.x; f[3] = b.y;
-    }
-}
 
 // Four consecutive elements at a 32-bit element offset of a uniform base
 // (element alignment only: the loads are 16-byte vector loads, which gfx950
@@ -82,46 +54,12 @@ __device__ inline void ld4_at(const double* p, uint32_t off, double (&r)[4]) {
 
 __device__ inline bool is_identity(int flags) { return (flags & (F_ID_A | F_ID_B)) != 0; }
 
-// Calls f(std::integral_constant<int, j>) for a run-time j in [0, 6): one
-// case per value, opened and closed by distinct empty asm comments so that
-// the compiler can neither merge the cases nor hoist or sink their common
-// code into one block that indexes a register array with j (which it would
-// lower to selects or scratch memory).
-#define DMRG_TILE_CASE(n)                                  \
-    case n:                                                \
-        asm volatile("; tile " #n " begin");               \
-        f(std::integral_constant<int, n>{});               \
-        asm volatile("; tile " #n " end");                 \
-        break;
-template <typename F>
-__device__ __forceinline__ void tile_switch(int j, F&& f) {
-    switch (j) {
-        DMRG_TILE_CASE(0)
-        DMRG_TILE_CASE(1)
-        DMRG_TILE_CASE(2)
-        DMRG_TILE_CASE(3)
-        DMRG_TILE_CASE(4)
-#if DMRG_MAX_ROWS > 80
-        DMRG_TILE_CASE(5)
-#endif
-        default: break;
-    }
-}
-#undef DMRG_TILE_CASE
-
 // Element (32-bit offset) of a uniform base pointer: the byte offset stays
 // 32-bit so the load takes the scalar-base + vector-offset form.
 template <typename T>
 __device__ inline T ld_at(const T* p, uint32_t off) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off * (uint32_t)sizeof(T));
 }
-
-// A chunk of a task's work, all through the same LDS pipeline:
-//   kind 0: A . B of contribution c over k0..k0+15,
-//   kind 2: identity contribution c (U += alpha * operand), U rows k0..k0+15,
-//   kind 1: X . U over U rows k0..k0+15 of group g;  g < 0: none.
-// X . U chunks come last in their group.
-enum { CH_AB = 0, CH_XU = 1, CH_ID = 2 };
 
 // Group / contribution records of a task.  LR = false: straight from global
 // memory (scalar loads).  LR = true: the task's records were copied to LDS
@@ -170,100 +108,6 @@ __device__ inline int stage_records(const Group* __restrict__ groups, const Cont
     return cb;
 }
 
-// Position of the chunk walk over a task's groups and contributions, with
-// the fields of the current group and contribution held in scalar
-// registers: advancing within a contribution (or within the X . U pass of a
-// group) reads no memory, so records are read only at boundaries.
-template <typename T>
-struct Cursor {
-    int g, c, k0, kind;        // g < 0: no chunk
-    int mu, gflags, ldx, c1;   // group g
-    int64_t x_off;
-    T x_coef, xid;
-    int64_t a_off, b_off;      // contribution c
-    T alpha;
-    int lda, ldb, k, cflags;
-};
-
-template <typename T, class RC>
-__device__ inline void cursor_contrib(const RC& R, Cursor<T>& q, int c) {
-    const Contrib ct = R.contrib(c);
-    q.c = c;
-    q.a_off = ct.a_off;
-    q.b_off = ct.b_off;
-    q.alpha = (T)ct.alpha;
-    q.lda = ct.lda;
-    q.ldb = ct.ldb;
-    q.k = ct.k;
-    q.cflags = ct.flags;
-    q.k0 = 0;
-    q.kind = is_identity(ct.flags) ? CH_ID : CH_AB;
-}
-
-// the first chunk of the first group >= g (of g < g1) that has one
-template <typename T, class RC>
-__device__ inline void cursor_group(const RC& R, Cursor<T>& q, int g, int g1) {
-    for (; g < g1; ++g) {
-        const Group gr = R.group(g);
-        q.g = g;
-        q.mu = gr.mu;
-        q.gflags = gr.flags;
-        q.ldx = gr.ldx;
-        q.c1 = gr.c1;
-        q.x_off = gr.x_off;
-        q.x_coef = (T)gr.x_coef;
-        q.xid = (T)gr.xid_coef;
-        if (gr.c1 > gr.c0) {
-            cursor_contrib(R, q, gr.c0);
-            return;
-        }
-        if (gr.flags & G_HAS_X) {
-            q.k0 = 0;
-            q.kind = CH_XU;
-            return;
-        }
-    }
-    q.g = -1;
-}
-
-template <int KC, typename T, class RC>
-__device__ inline void cursor_next(const RC& R, Cursor<T>& q, int g1) {
-    if (q.kind == CH_XU) {
-        if (q.k0 + KC < q.mu) { q.k0 += KC; return; }
-    } else {
-        const int extent = q.kind == CH_AB ? q.k : q.mu;
-        if (q.k0 + KC < extent) { q.k0 += KC; return; }
-        if (q.c + 1 < q.c1) { cursor_contrib(R, q, q.c + 1); return; }
-        if (q.gflags & G_HAS_X) { q.k0 = 0; q.kind = CH_XU; return; }
-    }
-    cursor_group(R, q, q.g + 1, g1);
-}
-
-// Element e of a KC-wide chunk slot (KC = 16 or 32).  kcontig: KC consecutive
-// threads take KC consecutive inner indices (kk) of one row; otherwise 16
-// consecutive rows of one kk.  Rows of the slot are 16 * (number of row tiles).
-template <int KC>
-__device__ inline void chunk_elem(int e, bool kcontig, int& row, int& kk) {
-    constexpr int SH = KC == 32 ? 5 : 4;
-    if (kcontig) { row = e >> SH; kk = e & (KC - 1); }
-    else { row = ((e >> (SH + 4)) << 4) | (e & 15); kk = (e >> 4) & (KC - 1); }
-}
-
-// Minimum waves per SIMD each tile-kernel instantiation is compiled for
-// (caps registers at 512 / waves), chosen by measurement: FP32 tiles of three
-// or more slices fit 128 registers; narrower FP32 tiles and FP64 tiles need more.
-// k per LDS chunk.  The kernel supports 16 and 32; 16 is used: a 32-wide
-// chunk halves the chunks and barriers per MFMA, but its extra registers cost
-// a wave per SIMD, which measured slower on the 54-orbital workload.
-template <typename T, int NCT> struct ChunkK { static constexpr int kc = 16; };
-
-#ifndef DMRG_OCC3_MAX
-#define DMRG_OCC3_MAX 3
-#endif
-template <typename T, int NCT> struct Occ {
-    static constexpr int waves = sizeof(T) == 4 ? ((NCT <= DMRG_OCC3_MAX || ChunkK<T, NCT>::kc == 32) ? 3 : 4) : 2;
-};
-
 // The buffer table is read through the kernel-argument segment so that an
 // index known only at run time becomes a scalar load rather than a select
 // over registers; the table is the kernel's first argument (offset 0).
@@ -274,284 +118,16 @@ __device__ inline const T* base_ptr(int buf, int vec) {
     return b->p[buf] + (int64_t)vec * b->vstride[buf];
 }
 
-template <typename T, int NCT, bool LR>
-__global__ __launch_bounds__(64 * NCT, (Occ<T, NCT>::waves)) void tile_kernel(Bases<T> Bargs,
-                                                                               const Task* __restrict__ tasks,
-                                                                               int ntask,
-                                                                               const Group* __restrict__ groups,
-                                                                               const Contrib* __restrict__ contribs) {
-    using V4 = typename Mfma<T>::v4;
-    constexpr int NT = 64 * NCT;
-    constexpr int KC = ChunkK<T, NCT>::kc;        // k per LDS chunk
-    constexpr int KS = KC / 16;                   // 16-k MFMA groups per chunk
-    constexpr int LD = Lds<T, KC>::ld;
-    constexpr int AR = 16 * kRT;                  // rows of the A / X slot
-    constexpr int EA = (AR * KC + NT - 1) / NT;   // A-slot elements per thread
-    __shared__ __attribute__((aligned(16))) T sA[2][AR * LD];
-    __shared__ Group sG[LR ? kRecG : 1];
-    __shared__ Contrib sC[LR ? kRecC : 1];
-    (void)Bargs;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = tid >> 6;
-    const int lr = lane & 15;
-    const int lk = lane >> 4;
-    if ((int)blockIdx.x >= ntask) return;
-    const Task tk = tasks[blockIdx.x];
-    const int vec = blockIdx.y;
-    const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
-    const int nrm = (tk.m + 15) >> 4;                // output row tiles
-    const int mycol = 16 * w + lr;                   // tile-local column of this lane
-    Recs<LR> R;
-    if constexpr (LR) {
-        const int cb = stage_records(groups, contribs, tk.g0, tk.g1, sG, sC, tid, NT);
-        __syncthreads();
-        R = Recs<true>{sG, sC, tk.g0, cb};
-    } else {
-        R = Recs<false>{groups, contribs};
-    }
-
-    V4 acc[kRT], U[kRT];
-#pragma unroll
-    for (int i = 0; i < kRT; ++i) acc[i] = U[i] = V4{0, 0, 0, 0};
-    // Operands of the next chunk in flight: every load is issued unconditionally
-    // (out-of-range elements read offset 0 of their block, which is always valid)
-    // and masked when written to LDS, so no wait is needed before the MFMAs of
-    // the current chunk.
-    // The B operand (this wave's 16 columns) is not shared between waves: it is
-    // loaded straight into MFMA fragment registers (rb, in flight; rbc, the
-    // current chunk's copy) instead of through LDS.  For an A . B chunk lane
-    // (c, g) holds B[k0 + 16q + 4g + s][c] (q < KS, s < 4); for an identity
-    // chunk it holds operand rows k0 + 16q + row(g, v) of column c, the
-    // accumulator layout of U.
-    T ra[EA], rb[4 * KS], rbc[4 * KS];
-    uint32_t a_ok = 0, b_ok = 0, b_okc = 0;   // element valid
-    T a_scale = 0, b_scale = 0, b_scalec = 0;
-    bool a_tr = false;                        // layout of the chunk held in ra
-    int a_rows = 0;
-    static_assert(EA <= 32, "mask width");
-
-    // global -> registers: the operands of chunk ch
-    auto load = [&](const Cursor<T>& ch) {
-        if (ch.kind == CH_XU) {
-            const T* p = base_ptr<T>(ch.gflags & 7, vec) + ch.x_off;
-            const int ld = ch.ldx, rows = tk.m, K = ch.mu;
-            const bool tr = (ch.gflags & G_TRANS_X) != 0;
-            const int nel = nrm * 16 * KC;
-            uint32_t ok = 0;
-#pragma unroll
-            for (int i = 0; i < EA; ++i) {
-                const int e = tid + i * NT;
-                int row, kk;
-                chunk_elem<KC>(e, !tr, row, kk);
-                const int k = ch.k0 + kk;
-                const bool v = e < nel && row < rows && k < K;
-                ra[i] = ld_at(p, v ? (tr ? (uint32_t)(k * ld + row) : (uint32_t)(row * ld + k)) : 0u);
-                ok |= (uint32_t)v << i;
-            }
-            a_ok = ok;
-            a_scale = ch.x_coef;
-            a_tr = tr;
-            a_rows = rows;
-            return;
-        }
-        if (ch.kind == CH_AB) {
-            const T* p = base_ptr<T>(ch.cflags & 7, vec) + ch.a_off;
-            const T* q = base_ptr<T>((ch.cflags >> 3) & 7, vec) + ch.b_off;
-            const bool ta = (ch.cflags & F_TRANS_A) != 0, tb = (ch.cflags & F_TRANS_B) != 0;
-            const int lda = ch.lda, ldb = ch.ldb, rows = ch.mu, K = ch.k;
-            const int nel = ((rows + 15) >> 4) * 16 * KC;
-            uint32_t ok = 0;
-#pragma unroll
-            for (int i = 0; i < EA; ++i) {
-                const int e = tid + i * NT;
-                int row, kk;
-                chunk_elem<KC>(e, !ta, row, kk);
-                const int k = ch.k0 + kk;
-                const bool v = e < nel && row < rows && k < K;
-                ra[i] = ld_at(p, v ? (ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k)) : 0u);
-                ok |= (uint32_t)v << i;
-            }
-            a_ok = ok;
-            ok = 0;
-            const int c = tk.col0 + mycol;
-            if (KS == 1 && tb && ch.k0 + KC <= K) {
-                // a full chunk of a transposed operand: the lane's four k are
-                // consecutive in the operand row, one vector load
-                const bool v = mycol < ncv;
-                T r4[4];
-                ld4_at(q, v ? (uint32_t)(c * ldb + ch.k0 + 4 * lk) : 0u, r4);
-#pragma unroll
-                for (int s = 0; s < 4; ++s) rb[s] = r4[s];
-                ok = v ? 0xfu : 0u;
-            } else {
-#pragma unroll
-                for (int s = 0; s < 4 * KS; ++s) {
-                    const int k = ch.k0 + 16 * (s >> 2) + 4 * lk + (s & 3);
-                    const bool v = mycol < ncv && k < K;
-                    rb[s] = ld_at(q, v ? (tb ? (uint32_t)(c * ldb + k) : (uint32_t)(k * ldb + c)) : 0u);
-                    ok |= (uint32_t)v << s;
-                }
-            }
-            b_ok = ok;
-            a_scale = ch.alpha;
-            b_scale = T(1);
-            a_tr = ta;
-            a_rows = rows;
-            return;
-        }
-        // identity contribution: rows k0 + row(g, v) of alpha * operand (or of
-        // alpha * I shifted by a_off), this lane's column
-        const bool ida = (ch.cflags & F_ID_A) != 0, idb = (ch.cflags & F_ID_B) != 0;
-        const T* p = ida ? base_ptr<T>((ch.cflags >> 3) & 7, vec) + ch.b_off
-                         : base_ptr<T>(ch.cflags & 7, vec) + ch.a_off;
-        const bool tp = ida ? (ch.cflags & F_TRANS_B) != 0 : (ch.cflags & F_TRANS_A) != 0;
-        const int ld = ida ? ch.ldb : ch.lda;
-        const int c = tk.col0 + mycol;
-        uint32_t ok = 0;
-#pragma unroll
-        for (int v4 = 0; v4 < 4 * KS; ++v4) {
-            const int row = ch.k0 + 16 * (v4 >> 2) + Mfma<T>::row(lk, v4 & 3);
-            const bool v = mycol < ncv && row < ch.mu;
-            if (ida && idb)   // a_off: diagonal offset of the identity
-                rb[v4] = ((int64_t)row + ch.a_off == c) ? T(1) : T(0);
-            else
-                rb[v4] = ld_at(p, v ? (tp ? (uint32_t)(c * ld + row) : (uint32_t)(row * ld + c)) : 0u);
-            ok |= (uint32_t)v << v4;
-        }
-        b_ok = ok;
-        b_scale = ch.alpha;
-    };
-    // registers -> LDS buffer b (masking and scaling here, after the loads landed)
-    auto store = [&](const auto& ch, int b) {
-        if (ch.kind != CH_XU) {   // B fragments of this chunk: masked and scaled copy
-#pragma unroll
-            for (int s = 0; s < 4 * KS; ++s) rbc[s] = ((b_ok >> s) & 1) ? b_scale * rb[s] : T(0);
-        }
-        if (ch.kind != CH_ID) {
-            const int nel = ((a_rows + 15) >> 4) * 16 * KC;
-#pragma unroll
-            for (int i = 0; i < EA; ++i) {
-                const int e = tid + i * NT;
-                if (e < nel) {
-                    int row, kk;
-                    chunk_elem<KC>(e, !a_tr, row, kk);
-                    sA[b][row * LD + (ch.kind == CH_XU ? xu_pos<T>(kk) : kk)] =
-                        ((a_ok >> i) & 1) ? a_scale * ra[i] : T(0);
-                }
-            }
-        }
-    };
-
-    // q: the chunk whose operands are loaded next; cur: the chunk computed
-    struct Cur { int g, kind, k0, mu; T xid; };
-    Cursor<T> q;
-    cursor_group(R, q, tk.g0, tk.g1);
-    if (q.g >= 0) load(q);
-    Cur cur{q.g, q.kind, q.k0, q.mu, q.xid};
-    int buf = 0, gcur = -1;
-    T xi = 0;   // identity-X coefficient of group gcur still to be applied (0 once applied)
-    while (cur.g >= 0) {
-        store(cur, buf);
-        __syncthreads();   // chunk cur complete in LDS; the buffer written next is free
-        cursor_next<KC>(R, q, tk.g1);
-        if (q.g >= 0) load(q);   // in flight during the MFMAs below
-        if (cur.g != gcur) {
-#pragma unroll
-            for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
-#pragma unroll
-            for (int i = 0; i < kRT; ++i) U[i] = V4{0, 0, 0, 0};
-            gcur = cur.g;
-            xi = cur.xid;
-        }
-        const T* A = sA[buf];
-        if (cur.kind == CH_AB) {
-            const int nru = (cur.mu + 15) >> 4;
-            const T* bf = rbc;
-            // row tiles in pairs: fragments of at most two tiles live at once
-#pragma unroll
-            for (int i = 0; i < kRT; ++i) {
-                if (i >= nru) continue;
-#pragma unroll
-                for (int q = 0; q < KS; ++q) {
-                    T af[4];
-                    lds_read4(A + (16 * i + lr) * LD + 16 * q + 4 * lk, af);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(af[s], bf[4 * q + s], U[i]);
-                }
-                if (i & 1) __builtin_amdgcn_sched_barrier(0);
-            }
-        } else if (cur.kind == CH_XU) {
-            if (cur.k0 == 0) {   // U is complete at the first X . U chunk
-#pragma unroll
-                for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
-                xi = 0;
-            }
-            // the chunk covers U row tiles j .. j + KS - 1
-            tile_switch(cur.k0 >> 4, [&](auto J) {
-                constexpr int j = decltype(J)::value;
-#pragma unroll
-                for (int i = 0; i < kRT; ++i) {
-                    if (i >= nrm) continue;
-                    T xf[4];
-                    lds_read4(A + (16 * i + lr) * LD + 4 * lk, xf);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[s], U[j][s], acc[i]);
-                    if constexpr (KS == 2 && j + 1 < kRT) {
-                        lds_read4(A + (16 * i + lr) * LD + 16 + 4 * lk, xf);
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[s], U[j + 1][s], acc[i]);
-                    }
-                    if (i & 1) __builtin_amdgcn_sched_barrier(0);
-                }
-            });
-        } else {
-            tile_switch(cur.k0 >> 4, [&](auto J) {
-                constexpr int j = decltype(J)::value;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) U[j][v] += rbc[v];
-                if constexpr (KS == 2 && j + 1 < kRT) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) U[j + 1][v] += rbc[4 + v];
-                }
-            });
-        }
-        buf ^= 1;
-        cur = Cur{q.g, q.kind, q.k0, q.mu, q.xid};
-    }
-#pragma unroll
-    for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
-
-    const int cbuf = tk.cbuf & 15;
-    const bool accum = (tk.cbuf >> 8) & 1;
-    const bool local = (tk.cbuf >> 9) & 1;   // partial slot: columns from 0
-    T* Cp = const_cast<T*>(base_ptr<T>(cbuf, vec)) + tk.c_off + (local ? 0 : tk.col0);
-    if (mycol < ncv) {
-#pragma unroll
-        for (int i = 0; i < kRT; ++i) {
-            if (i >= nrm) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * i + Mfma<T>::row(lk, v);
-                if (row < tk.m) {
-                    T* d = Cp + (uint32_t)(row * tk.ldc + mycol);
-                    *d = accum ? *d + acc[i][v] : acc[i][v];
-                }
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------------------
-// slice_kernel: the tasks of tile_kernel (one workgroup per output tile of
-// <= 80 rows x 16*NCT columns), but every wave computes its 16-column slice on
-// its own.  MFMA fragments are loaded straight from global memory into
-// operand registers -- one 16-byte vector load per lane and row tile where
-// the operand's layout puts the lane's four k next to each other -- so the
-// chunk loop has no LDS staging and no barrier.  The waves of a tile share a
-// workgroup (and a CU), so the A and X rows they all read come from L1 after
-// the first wave's miss.
+// slice_kernel: output tiles of <= 80 rows x 16*NCT columns.  Every wave
+// computes one 16-column slice of a tile on its own, four slices per
+// workgroup (consecutive slices of one task share a workgroup, and so the
+// CU's L1 for the A and X rows they all read).  MFMA fragments are loaded
+// straight from global memory into operand registers -- one 16-byte vector
+// load per lane and row tile where the operand's layout puts the lane's four
+// k next to each other -- so the chunk loop has no LDS staging and no barrier.
+// Small workgroups of independent waves matter: workgroups of five or six
+// waves reached fewer than two per CU.
 //
 // Per group: U = sum_c alpha_c A_c B_c over 16-k chunks; then U's rows past
 // mu (products of clamped A rows) are zeroed, the identity term xid * U is
@@ -984,22 +560,9 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
         }
 }
 
-#ifndef DMRG_SLICE
-#define DMRG_SLICE 1
-#endif
-#ifndef DMRG_SLICE_WAVE
-#define DMRG_SLICE_WAVE 0
-#endif
 template <typename T, bool LR>
 static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
                           int nvec, hipStream_t s) {
-    if (cls >= kNumTileClass && DMRG_SLICE_WAVE) {   // wave classes on the slice kernel
-        const int ct = (cls - kNumTileClass) % 2 + 1;
-        const dim3 grid((ntask * ct + 3) / 4, nvec), block(256);
-        if (ct == 1) hipLaunchKernelGGL((slice_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c);
-        else hipLaunchKernelGGL((slice_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c);
-        return (int)hipGetLastError();
-    }
     if (cls >= kNumTileClass) {   // wave classes: four tasks per workgroup
         const dim3 grid((ntask + 3) / 4, nvec), block(256);
         switch (cls - kNumTileClass) {
@@ -1011,27 +574,15 @@ static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, con
         }
         return (int)hipGetLastError();
     }
-    if (DMRG_SLICE) {   // four column slices per workgroup
-        const dim3 grid((ntask * (cls + 1) + 3) / 4, nvec), block(256);
-        switch (cls) {
-            case 0: hipLaunchKernelGGL((slice_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 1: hipLaunchKernelGGL((slice_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 2: hipLaunchKernelGGL((slice_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 3: hipLaunchKernelGGL((slice_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 4: hipLaunchKernelGGL((slice_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 5: hipLaunchKernelGGL((slice_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            default: return (int)hipErrorInvalidValue;
-        }
-        return (int)hipGetLastError();
-    }
-    const dim3 grid(ntask, nvec), block(64 * (cls + 1));
+    // tile classes: four column slices per workgroup
+    const dim3 grid((ntask * (cls + 1) + 3) / 4, nvec), block(256);
     switch (cls) {
-        case 0: hipLaunchKernelGGL((tile_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 1: hipLaunchKernelGGL((tile_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 2: hipLaunchKernelGGL((tile_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 3: hipLaunchKernelGGL((tile_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 4: hipLaunchKernelGGL((tile_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 5: hipLaunchKernelGGL((tile_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 0: hipLaunchKernelGGL((slice_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 1: hipLaunchKernelGGL((slice_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 2: hipLaunchKernelGGL((slice_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 3: hipLaunchKernelGGL((slice_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 4: hipLaunchKernelGGL((slice_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 5: hipLaunchKernelGGL((slice_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();

@@ -23,8 +23,8 @@
 namespace dmrgk {
 
 // Rows of an output tile and of U (inner dimension of X . U): five MFMA row
-// tiles, so that the FP32 accumulators of the wide tile kernels stay within
-// 128 registers (four waves per SIMD); taller tiles are split exactly.
+// tiles, so that a wave's FP32 accumulators, U and one chunk's fragments stay
+// within 128 registers (four waves per SIMD); taller tiles are split exactly.
 #ifndef DMRG_MAX_ROWS
 #define DMRG_MAX_ROWS 80
 #endif
@@ -70,7 +70,7 @@ struct Bases {
 };
 
 // Task classes.  Tile classes c < kNumTileClass: tiles of 16c+1 .. 16c+16
-// columns, run by c+1 waves (one per 16-column slice) with LDS staging.
+// columns, computed as c+1 independent 16-column slices (one wave each).
 // Wave classes kNumTileClass + (RT-1)*2 + (CT-1): tiles whose rows and U
 // rows fit 16*RT and whose columns fit 16*CT (RT, CT <= 2), one wave each.
 constexpr int kNumTileClass = kMaxCols / 16;
