@@ -139,40 +139,33 @@ __device__ inline const T* base_ptr(int buf, int vec) {
 #ifndef DMRG_SLICE_OCC64
 #define DMRG_SLICE_OCC64 2
 #endif
-// column slices per wave: FP32 waves take two (A loaded once for 32 columns),
-// FP64 waves one (two would not fit the registers)
-#ifndef DMRG_SLICE_CT32
-#define DMRG_SLICE_CT32 1
-#endif
-template <typename T> struct SliceCols { static constexpr int value = sizeof(T) == 4 ? DMRG_SLICE_CT32 : 1; };
 template <typename T> struct SliceOcc {
     static constexpr int waves = sizeof(T) == 4 ? DMRG_SLICE_OCC32 : DMRG_SLICE_OCC64;
 };
 
 
-template <typename T, int NCT, int CT, bool LR>
+template <typename T, int NCT, bool LR>
 __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<T> Bargs,
                                                                         const Task* __restrict__ tasks,
                                                                         int ntask,
                                                                         const Group* __restrict__ groups,
                                                                         const Contrib* __restrict__ contribs) {
     using V4 = typename Mfma<T>::v4;
-    constexpr int NU = (NCT + CT - 1) / CT;   // units (waves) per task
     __shared__ Group sG[LR ? 4 : 1][LR ? kRecG : 1];
     __shared__ Contrib sC[LR ? 4 : 1][LR ? kRecC : 1];
     (void)Bargs;
 
-    // four units per workgroup: wave wv takes unit u = 4 blockIdx.x + wv, the
-    // CT column slices from slice CT * (u % NU) of task u / NU
+    // four slices per workgroup: wave wv takes unit u = 4 blockIdx.x + wv,
+    // column slice u % NCT of task u / NCT
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
     const int u = blockIdx.x * 4 + wv;
-    if (u >= ntask * NU) return;
-    const int w = CT * (u % NU);   // first column slice of this wave
+    if (u >= ntask * NCT) return;
+    const int w = u % NCT;
     const int lr0 = lane & 15;
     const int lk0 = lane >> 4;
-    const Task tk = tasks[u / NU];
+    const Task tk = tasks[u / NCT];
     const int vec = blockIdx.y;
     const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
     const int nrm = (tk.m + 15) >> 4;                // output row tiles
@@ -187,11 +180,9 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
         R = Recs<false>{groups, contribs};
     }
 
-    V4 acc[kRT][CT];
+    V4 acc[kRT];
 #pragma unroll
-    for (int i = 0; i < kRT; ++i)
-#pragma unroll
-        for (int j = 0; j < CT; ++j) acc[i][j] = V4{0, 0, 0, 0};
+    for (int i = 0; i < kRT; ++i) acc[i] = V4{0, 0, 0, 0};
     // The lane coordinates are passed through an empty asm inside each loop,
     // so that the compiler recomputes the cheap per-lane bounds there instead
     // of hoisting dozens of lane masks out of the loops (which spilled).
@@ -201,44 +192,39 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
         const Group gr = R.group(g);
         const int mu = gr.mu;
         const int nru = (mu + 15) >> 4;   // row tiles of U
-        V4 U[kRT][CT];
+        V4 U[kRT];
 #pragma unroll
-        for (int i = 0; i < kRT; ++i)
-#pragma unroll
-            for (int j = 0; j < CT; ++j) U[i][j] = V4{0, 0, 0, 0};
+        for (int i = 0; i < kRT; ++i) U[i] = V4{0, 0, 0, 0};
         for (int c = gr.c0; c < gr.c1; ++c) {
             const Contrib ct = R.contrib(c);
             const T alpha = (T)ct.alpha;
             if (is_identity(ct.flags)) {
-                // U rows row(g, v) of tile i += alpha * operand (or alpha * shifted I), this lane's columns
+                // U rows row(g, v) of tile i += alpha * operand (or alpha * shifted I), this lane's column
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                const int gcol = tk.col0 + 16 * w + lr;
+                const bool colok = 16 * w + lr < ncv;
                 const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
                 const T* P = ida ? base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off
                                  : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
                 const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
                 const int ld = ida ? ct.ldb : ct.lda;
 #pragma unroll
-                for (int j = 0; j < CT; ++j) {
-                    const int lr = opaque(lr0), lk = opaque(lk0);
-                    const int gcol = tk.col0 + 16 * (w + j) + lr;
-                    const bool colok = 16 * (w + j) + lr < ncv;
+                for (int i = 0; i < kRT; ++i) {
+                    if (i >= nru) continue;
+                    T x[4];
 #pragma unroll
-                    for (int i = 0; i < kRT; ++i) {
-                        if (i >= nru) continue;
-                        T x[4];
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * i + Mfma<T>::row(lk, v);
+                        const bool ok = row < mu && colok;
+                        if (ida && idb)   // a_off: diagonal offset of the identity (within the block)
+                            x[v] = (row + (int)ct.a_off == gcol) ? T(1) : T(0);
+                        else
+                            x[v] = ld_at(P, ok ? (tp ? (uint32_t)(gcol * ld + row) : (uint32_t)(row * ld + gcol)) : 0u);
+                    }
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = 16 * i + Mfma<T>::row(lk, v);
-                            const bool ok = row < mu && colok;
-                            if (ida && idb)   // a_off: diagonal offset of the identity (within the block)
-                                x[v] = (row + (int)ct.a_off == gcol) ? T(1) : T(0);
-                            else
-                                x[v] = ld_at(P, ok ? (tp ? (uint32_t)(gcol * ld + row) : (uint32_t)(row * ld + gcol)) : 0u);
-                        }
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = 16 * i + Mfma<T>::row(lk, v);
-                            U[i][j][v] += (row < mu && colok) ? alpha * x[v] : T(0);
-                        }
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * i + Mfma<T>::row(lk, v);
+                        U[i][v] += (row < mu && colok) ? alpha * x[v] : T(0);
                     }
                 }
                 continue;
@@ -247,13 +233,13 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
             const T* Bp = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
-            for (int k0 = 0; k0 < K; k0 += 16) {
-                // all fragment loads of the chunk first (clamped when out of
-                // range), then one wait and the MFMAs.  Lane (r, g) takes
-                // k = k0 + 4g + s: rows 16i + r of A, column 16 (w + j) + r of B.
+            // the fragment loads of the chunk at k0 (clamped when out of range).
+            // Lane (r, g) takes k = k0 + 4g + s: rows 16i + r of A, column gcol of B.
+            auto fetch = [&](int k0, T (&fa)[kRT][4], T (&fb)[4]) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
+                const int gcol = tk.col0 + 16 * w + lr;
+                const bool colok = 16 * w + lr < ncv;
                 const bool full = k0 + 16 <= K;
-                T fa[kRT][4], fb[CT][4];
 #pragma unroll
                 for (int i = 0; i < kRT; ++i) {
                     if (i >= nru) continue;
@@ -270,37 +256,36 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
                         }
                     }
                 }
+                if (tb && full) {
+                    ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + k0 + 4 * lk) : 0u, fb);
+                } else {
 #pragma unroll
-                for (int j = 0; j < CT; ++j) {
-                    const int gcol = tk.col0 + 16 * (w + j) + lr;
-                    const bool colok = 16 * (w + j) + lr < ncv;
-                    if (tb && full) {
-                        ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + k0 + 4 * lk) : 0u, fb[j]);
-                    } else {
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            const int k = k0 + 4 * lk + s;
-                            const bool ok = colok && k < K;
-                            fb[j][s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gcol * ldb + k) : (uint32_t)(k * ldb + gcol)) : 0u);
-                        }
+                    for (int s = 0; s < 4; ++s) {
+                        const int k = k0 + 4 * lk + s;
+                        const bool ok = colok && k < K;
+                        fb[s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gcol * ldb + k) : (uint32_t)(k * ldb + gcol)) : 0u);
                     }
                 }
-                // k past K or a column past the tile: zero B (A's clamped rows
-                // only reach U rows past mu, zeroed below)
+            };
+            // U += alpha * A . B of the chunk at k0.  k past K or a column past
+            // the tile: B is zeroed (A's clamped rows only reach U rows past mu,
+            // zeroed below).
+            auto mmas = [&](int k0, T (&fa)[kRT][4], T (&fb)[4]) {
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                const bool colok = 16 * w + lr < ncv;
 #pragma unroll
-                for (int j = 0; j < CT; ++j) {
-                    const bool colok = 16 * (w + j) + lr < ncv;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) fb[j][s] = (colok && k0 + 4 * lk + s < K) ? alpha * fb[j][s] : T(0);
-                }
+                for (int s = 0; s < 4; ++s) fb[s] = (colok && k0 + 4 * lk + s < K) ? alpha * fb[s] : T(0);
 #pragma unroll
                 for (int i = 0; i < kRT; ++i) {
                     if (i >= nru) continue;
 #pragma unroll
-                    for (int s = 0; s < 4; ++s)
-#pragma unroll
-                        for (int j = 0; j < CT; ++j) U[i][j] = Mfma<T>::mma(fa[i][s], fb[j][s], U[i][j]);
+                    for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(fa[i][s], fb[s], U[i]);
                 }
+            };
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                T fa[kRT][4], fb[4];
+                fetch(k0, fa, fb);
+                mmas(k0, fa, fb);
             }
         }
         {
@@ -309,16 +294,12 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
             for (int i = 0; i < kRT; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    if (16 * i + Mfma<T>::row(lk, v) >= mu)
-#pragma unroll
-                        for (int j = 0; j < CT; ++j) U[i][j][v] = T(0);
+                    if (16 * i + Mfma<T>::row(lk, v) >= mu) U[i][v] = T(0);
         }
         if (gr.xid_coef != 0.0) {
             const T xi = (T)gr.xid_coef;
 #pragma unroll
-            for (int i = 0; i < kRT; ++i)
-#pragma unroll
-                for (int j = 0; j < CT; ++j) acc[i][j] += xi * U[i][j];
+            for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
         }
         if (gr.flags & G_HAS_X) {
             const T* Xp = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
@@ -326,9 +307,7 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
             const T xc = (T)gr.x_coef;
             const int ldx = gr.ldx;
 #pragma unroll
-            for (int i = 0; i < kRT; ++i)
-#pragma unroll
-                for (int j = 0; j < CT; ++j) U[i][j] *= xc;
+            for (int i = 0; i < kRT; ++i) U[i] *= xc;
             // X . U over U's row tiles q: lane (r, g) takes X rows 16i + r,
             // k = 16q + row(g, s), the rows U's accumulator holds in the lane
 #pragma unroll
@@ -357,9 +336,7 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
                 for (int i = 0; i < kRT; ++i) {
                     if (i >= nrm) continue;
 #pragma unroll
-                    for (int s = 0; s < 4; ++s)
-#pragma unroll
-                        for (int j = 0; j < CT; ++j) acc[i][j] = Mfma<T>::mma(xf[i][s], U[q][j][s], acc[i][j]);
+                    for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[i][s], U[q][s], acc[i]);
                 }
                 __builtin_amdgcn_sched_barrier(0);   // one row tile of U at a time
             }
@@ -371,10 +348,8 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
     const bool local = (tk.cbuf >> 9) & 1;   // partial slot: columns from 0
     T* Cp = const_cast<T*>(base_ptr<T>(cbuf, vec)) + tk.c_off + (local ? 0 : tk.col0);
     const int lk = lk0;
-#pragma unroll
-    for (int j = 0; j < CT; ++j) {
-        const int mycol = 16 * (w + j) + lr0;   // tile-local column of this lane
-        if (mycol >= ncv) continue;
+    const int mycol = 16 * w + lr0;   // tile-local column of this lane
+    if (mycol < ncv) {
 #pragma unroll
         for (int i = 0; i < kRT; ++i) {
             if (i >= nrm) continue;
@@ -383,7 +358,7 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
                 const int row = 16 * i + Mfma<T>::row(lk, v);
                 if (row < tk.m) {
                     T* d = Cp + (uint32_t)(row * tk.ldc + mycol);
-                    *d = accum ? *d + acc[i][j][v] : acc[i][j][v];
+                    *d = accum ? *d + acc[i][v] : acc[i][v];
                 }
             }
         }
@@ -599,16 +574,15 @@ static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, con
         }
         return (int)hipGetLastError();
     }
-    // tile classes: four units of CT column slices per workgroup
-    constexpr int CT = SliceCols<T>::value;
-    const dim3 grid((ntask * ((cls + CT) / CT) + 3) / 4, nvec), block(256);
+    // tile classes: four column slices per workgroup
+    const dim3 grid((ntask * (cls + 1) + 3) / 4, nvec), block(256);
     switch (cls) {
-        case 0: hipLaunchKernelGGL((slice_kernel<T, 1, CT, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 1: hipLaunchKernelGGL((slice_kernel<T, 2, CT, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 2: hipLaunchKernelGGL((slice_kernel<T, 3, CT, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 3: hipLaunchKernelGGL((slice_kernel<T, 4, CT, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 4: hipLaunchKernelGGL((slice_kernel<T, 5, CT, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 5: hipLaunchKernelGGL((slice_kernel<T, 6, CT, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 0: hipLaunchKernelGGL((slice_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 1: hipLaunchKernelGGL((slice_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 2: hipLaunchKernelGGL((slice_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 3: hipLaunchKernelGGL((slice_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 4: hipLaunchKernelGGL((slice_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 5: hipLaunchKernelGGL((slice_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
