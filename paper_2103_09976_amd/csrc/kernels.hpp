@@ -2,7 +2,7 @@
 //
 // Everything heavy (blocking + transformation, the normal->complementary
 // transform, the integral-weighted operator sums and H_eff psi) is expressed
-// as one kind of work: an output tile C (up to 80 rows x 96 columns of a
+// as one kind of work: an output tile C (up to 96 rows x 96 columns of a
 // sector block) accumulated as
 //
 //     C = sum_groups [ x_coef * X_g . U_g + xid_coef * U_g ],
@@ -22,11 +22,13 @@
 
 namespace dmrgk {
 
-// Rows of an output tile and of U (inner dimension of X . U): five MFMA row
+// Rows of an output tile and of U (inner dimension of X . U): six MFMA row
 // tiles, so that a wave's FP32 accumulators, U and one chunk's fragments stay
-// within 128 registers (four waves per SIMD); taller tiles are split exactly.
+// within 168 registers (three waves per SIMD); taller tiles are split
+// exactly.  Each split row tile recomputes U, so taller tiles pay off on tall
+// sector blocks.
 #ifndef DMRG_MAX_ROWS
-#define DMRG_MAX_ROWS 80
+#define DMRG_MAX_ROWS 96
 #endif
 constexpr int kMaxRows = DMRG_MAX_ROWS;
 constexpr int kMaxCols = 96;     // columns of an output tile
