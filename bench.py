@@ -31,10 +31,10 @@ PROFILES = os.path.join(ROOT, "profiles")
 def launch_kernel_name(kind: int, prec: str = "float") -> str:
     """Kernel of launch slot `kind` of one H_eff product (see dmrg_heff_profile)."""
     slot, lr = kind & 255, "true" if kind & 256 else "false"
-    if slot < 6:
-        return f"slice_kernel<{prec}, {slot + 1}, {lr}>"
-    if slot < 10:
-        rt, ct = divmod(slot - 6, 2)
+    if slot < 12:
+        return f"slice_kernel<{prec}, {slot % 6 + 1}, {5 if slot < 6 else 6}, {lr}>"
+    if slot < 16:
+        rt, ct = divmod(slot - 12, 2)
         return f"wave_kernel<{prec}, {rt + 1}, {ct + 1}, {lr}>"
     return f"reduce_kernel<{prec}>"
 

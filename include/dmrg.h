@@ -197,11 +197,13 @@ int32_t dmrg_heff_terms(const dmrg_heff* H, int32_t* n2, int32_t* n1, int32_t* n
  * launch.  For launch i < n (n >= DMRG_HEFF_LAUNCHES): ms[i] = its duration,
  * flops[i] = the useful MFMA flops of its tiles (2*m*mu*cols per X.U and
  * 2*mu*k*cols per A.B, padding and identities excluded), kind[i] = kernel
- * kind in bits 0-7 (0..5: LDS tile kernel with 1..6 waves, 6..9: one-wave
- * kernel with (rows, cols) tiles of (16,16), (16,32), (32,16), (32,32), 10:
- * partial-tile reduction) | 256 when the task records are staged in LDS.  Launches with no work report ms = 0.  Synchronizes `stream`.
+ * kind in bits 0-7 (0..5: slice kernel, tiles of 1..6 16-column slices and
+ * at most 80 rows; 6..11: the same with at most 96 rows; 12..15: one-wave
+ * kernel with (rows, cols) tiles of (16,16), (16,32), (32,16), (32,32); 16:
+ * partial-tile reduction) | 256 when the task records are staged in LDS.
+ * Launches with no work report ms = 0.  Synchronizes `stream`.
  * Returns the number of launches (>= 0) or a negative dmrg_status. */
-#define DMRG_HEFF_LAUNCHES 11
+#define DMRG_HEFF_LAUNCHES 17
 int32_t dmrg_heff_profile(dmrg_heff* H, int32_t precision, const void* psi, void* sigma, int32_t n, float* ms,
                           double* flops, int32_t* kind, void* stream);
 

@@ -34,7 +34,6 @@ template <> struct Mfma<float> {
     __device__ static constexpr int row(int lk, int v) { return 4 * lk + v; }
 };
 
-constexpr int kRT = kMaxRows / 16;   // row tiles of a task
 
 // Four consecutive elements at a 32-bit element offset of a uniform base
 // (element alignment only: the loads are 16-byte vector loads, which gfx950
@@ -133,21 +132,15 @@ __device__ inline const T* base_ptr(int buf, int vec) {
 // mu (products of clamped A rows) are zeroed, the identity term xid * U is
 // added, U is scaled by x_coef and C += X . U runs over U's row tiles.
 // ---------------------------------------------------------------------------
-// Waves per SIMD the slice kernel is compiled for: FP32 3 (152 registers at
-// 96-row tiles, no spills), FP64 2.
-#ifndef DMRG_SLICE_OCC32
-#define DMRG_SLICE_OCC32 3
-#endif
-#ifndef DMRG_SLICE_OCC64
-#define DMRG_SLICE_OCC64 2
-#endif
-template <typename T> struct SliceOcc {
-    static constexpr int waves = sizeof(T) == 4 ? DMRG_SLICE_OCC32 : DMRG_SLICE_OCC64;
+// Waves per SIMD the slice kernel is compiled for: FP32 4 for tiles of five
+// row tiles (128 registers), 3 for six (152 registers, no spills); FP64 2.
+template <typename T, int RT> struct SliceOcc {
+    static constexpr int waves = sizeof(T) == 4 ? (RT <= 5 ? 4 : 3) : 2;
 };
 
 
-template <typename T, int NCT, bool LR>
-__global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<T> Bargs,
+template <typename T, int NCT, int RT, bool LR>
+__global__ __launch_bounds__(256, (SliceOcc<T, RT>::waves)) void slice_kernel(Bases<T> Bargs,
                                                                         const Task* __restrict__ tasks,
                                                                         int ntask,
                                                                         const Group* __restrict__ groups,
@@ -182,9 +175,9 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
         R = Recs<false>{groups, contribs};
     }
 
-    V4 acc[kRT];
+    V4 acc[RT];
 #pragma unroll
-    for (int i = 0; i < kRT; ++i) acc[i] = V4{0, 0, 0, 0};
+    for (int i = 0; i < RT; ++i) acc[i] = V4{0, 0, 0, 0};
     // The lane coordinates are passed through an empty asm inside each loop,
     // so that the compiler recomputes the cheap per-lane bounds there instead
     // of hoisting dozens of lane masks out of the loops (which spilled).
@@ -194,9 +187,9 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
         const Group gr = R.group(g);
         const int mu = gr.mu;
         const int nru = (mu + 15) >> 4;   // row tiles of U
-        V4 U[kRT];
+        V4 U[RT];
 #pragma unroll
-        for (int i = 0; i < kRT; ++i) U[i] = V4{0, 0, 0, 0};
+        for (int i = 0; i < RT; ++i) U[i] = V4{0, 0, 0, 0};
         for (int c = gr.c0; c < gr.c1; ++c) {
             const Contrib ct = R.contrib(c);
             const T alpha = (T)ct.alpha;
@@ -211,7 +204,7 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
                 const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
                 const int ld = ida ? ct.ldb : ct.lda;
 #pragma unroll
-                for (int i = 0; i < kRT; ++i) {
+                for (int i = 0; i < RT; ++i) {
                     if (i >= nru) continue;
                     T x[4];
 #pragma unroll
@@ -237,13 +230,13 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
             // the fragment loads of the chunk at k0 (clamped when out of range).
             // Lane (r, g) takes k = k0 + 4g + s: rows 16i + r of A, column gcol of B.
-            auto fetch = [&](int k0, T (&fa)[kRT][4], T (&fb)[4]) {
+            auto fetch = [&](int k0, T (&fa)[RT][4], T (&fb)[4]) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const int gcol = tk.col0 + 16 * w + lr;
                 const bool colok = 16 * w + lr < ncv;
                 const bool full = k0 + 16 <= K;
 #pragma unroll
-                for (int i = 0; i < kRT; ++i) {
+                for (int i = 0; i < RT; ++i) {
                     if (i >= nru) continue;
                     const int row = 16 * i + lr;
                     const bool rok = row < mu;
@@ -272,20 +265,20 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
             // U += alpha * A . B of the chunk at k0.  k past K or a column past
             // the tile: B is zeroed (A's clamped rows only reach U rows past mu,
             // zeroed below).
-            auto mmas = [&](int k0, T (&fa)[kRT][4], T (&fb)[4]) {
+            auto mmas = [&](int k0, T (&fa)[RT][4], T (&fb)[4]) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const bool colok = 16 * w + lr < ncv;
 #pragma unroll
                 for (int s = 0; s < 4; ++s) fb[s] = (colok && k0 + 4 * lk + s < K) ? alpha * fb[s] : T(0);
 #pragma unroll
-                for (int i = 0; i < kRT; ++i) {
+                for (int i = 0; i < RT; ++i) {
                     if (i >= nru) continue;
 #pragma unroll
                     for (int s = 0; s < 4; ++s) U[i] = Mfma<T>::mma(fa[i][s], fb[s], U[i]);
                 }
             };
             for (int k0 = 0; k0 < K; k0 += 16) {
-                T fa[kRT][4], fb[4];
+                T fa[RT][4], fb[4];
                 fetch(k0, fa, fb);
                 mmas(k0, fa, fb);
             }
@@ -293,7 +286,7 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
         {
             const int lk = opaque(lk0);
 #pragma unroll
-            for (int i = 0; i < kRT; ++i)
+            for (int i = 0; i < RT; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
                     if (16 * i + Mfma<T>::row(lk, v) >= mu) U[i][v] = T(0);
@@ -301,7 +294,7 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
         if (gr.xid_coef != 0.0) {
             const T xi = (T)gr.xid_coef;
 #pragma unroll
-            for (int i = 0; i < kRT; ++i) acc[i] += xi * U[i];
+            for (int i = 0; i < RT; ++i) acc[i] += xi * U[i];
         }
         if (gr.flags & G_HAS_X) {
             const T* Xp = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
@@ -309,17 +302,17 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
             const T xc = (T)gr.x_coef;
             const int ldx = gr.ldx;
 #pragma unroll
-            for (int i = 0; i < kRT; ++i) U[i] *= xc;
+            for (int i = 0; i < RT; ++i) U[i] *= xc;
             // X . U over U's row tiles q: lane (r, g) takes X rows 16i + r,
             // k = 16q + row(g, s), the rows U's accumulator holds in the lane
 #pragma unroll
-            for (int q = 0; q < kRT; ++q) {
+            for (int q = 0; q < RT; ++q) {
                 if (q >= nru) continue;
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const bool full = 16 * q + 16 <= mu;
-                T xf[kRT][4];
+                T xf[RT][4];
 #pragma unroll
-                for (int i = 0; i < kRT; ++i) {
+                for (int i = 0; i < RT; ++i) {
                     if (i >= nrm) continue;
                     const int row = 16 * i + lr;
                     const bool rok = row < tk.m;
@@ -335,7 +328,7 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
                     }
                 }
 #pragma unroll
-                for (int i = 0; i < kRT; ++i) {
+                for (int i = 0; i < RT; ++i) {
                     if (i >= nrm) continue;
 #pragma unroll
                     for (int s = 0; s < 4; ++s) acc[i] = Mfma<T>::mma(xf[i][s], U[q][s], acc[i]);
@@ -353,7 +346,7 @@ __global__ __launch_bounds__(256, (SliceOcc<T>::waves)) void slice_kernel(Bases<
     const int mycol = 16 * w + lr0;   // tile-local column of this lane
     if (mycol < ncv) {
 #pragma unroll
-        for (int i = 0; i < kRT; ++i) {
+        for (int i = 0; i < RT; ++i) {
             if (i >= nrm) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -576,15 +569,23 @@ static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, con
         }
         return (int)hipGetLastError();
     }
-    // tile classes: four column slices per workgroup
-    const dim3 grid((ntask * (cls + 1) + 3) / 4, nvec), block(256);
+    // tile classes: four column slices per workgroup; five row tiles for
+    // classes below kColClasses, six above
+    constexpr int RS = kShortRows / 16, RL = kMaxRows / 16;
+    const dim3 grid((ntask * (cls % kColClasses + 1) + 3) / 4, nvec), block(256);
     switch (cls) {
-        case 0: hipLaunchKernelGGL((slice_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 1: hipLaunchKernelGGL((slice_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 2: hipLaunchKernelGGL((slice_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 3: hipLaunchKernelGGL((slice_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 4: hipLaunchKernelGGL((slice_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 5: hipLaunchKernelGGL((slice_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 0: hipLaunchKernelGGL((slice_kernel<T, 1, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 1: hipLaunchKernelGGL((slice_kernel<T, 2, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 2: hipLaunchKernelGGL((slice_kernel<T, 3, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 3: hipLaunchKernelGGL((slice_kernel<T, 4, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 4: hipLaunchKernelGGL((slice_kernel<T, 5, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 5: hipLaunchKernelGGL((slice_kernel<T, 6, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 6: hipLaunchKernelGGL((slice_kernel<T, 1, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 7: hipLaunchKernelGGL((slice_kernel<T, 2, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 8: hipLaunchKernelGGL((slice_kernel<T, 3, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 9: hipLaunchKernelGGL((slice_kernel<T, 4, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 10: hipLaunchKernelGGL((slice_kernel<T, 5, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+        case 11: hipLaunchKernelGGL((slice_kernel<T, 6, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();

@@ -22,15 +22,17 @@
 
 namespace dmrgk {
 
-// Rows of an output tile and of U (inner dimension of X . U): six MFMA row
-// tiles, so that a wave's FP32 accumulators, U and one chunk's fragments stay
-// within 168 registers (three waves per SIMD); taller tiles are split
-// exactly.  Each split row tile recomputes U, so taller tiles pay off on tall
-// sector blocks.
+// Rows of an output tile and of U (inner dimension of X . U): at most six MFMA
+// row tiles; taller blocks are split exactly, and each split row tile
+// recomputes U.  Tiles whose rows all fit five row tiles (kShortRows) run a
+// kernel compiled for five: a wave's FP32 accumulators, U and one chunk's
+// fragments then fit 128 registers (four waves per SIMD) instead of 168
+// (three).
 #ifndef DMRG_MAX_ROWS
 #define DMRG_MAX_ROWS 96
 #endif
 constexpr int kMaxRows = DMRG_MAX_ROWS;
+constexpr int kShortRows = 80;
 constexpr int kMaxCols = 96;     // columns of an output tile
 constexpr int kMaxBuf = 9;       // buffer 8: partial tiles of split tasks
 
@@ -71,20 +73,27 @@ struct Bases {
     int64_t vstride[kMaxBuf];   // per-vector stride (batched vectors, grid.y)
 };
 
-// Task classes.  Tile classes c < kNumTileClass: tiles of 16c+1 .. 16c+16
-// columns, computed as c+1 independent 16-column slices (one wave each).
-// Wave classes kNumTileClass + (RT-1)*2 + (CT-1): tiles whose rows and U
-// rows fit 16*RT and whose columns fit 16*CT (RT, CT <= 2), one wave each.
-constexpr int kNumTileClass = kMaxCols / 16;
+// Task classes.  Tile classes c < kNumTileClass: tiles of 16n+1 .. 16n+16
+// columns (n = c % kColClasses), computed as n+1 independent 16-column slices
+// (one wave each), with rows (and U rows) up to kShortRows (c < kColClasses)
+// or kMaxRows.  Wave classes kNumTileClass + (RT-1)*2 + (CT-1): tiles whose
+// rows and U rows fit 16*RT and whose columns fit 16*CT (RT, CT <= 2), one
+// wave each.
+constexpr int kColClasses = kMaxCols / 16;
+constexpr int kNumTileClass = 2 * kColClasses;
 constexpr int kNumClass = kNumTileClass + 4;
 inline int col_class(int ncol) { return (ncol + 15) / 16 - 1; }
 // rows: max of the tile rows and of every group's mu
 inline int task_class(int rows, int ncol) {
     if (rows <= 32 && ncol <= 32) return kNumTileClass + ((rows + 15) / 16 - 1) * 2 + (ncol + 15) / 16 - 1;
-    return col_class(ncol);
+    return col_class(ncol) + (rows > kShortRows ? kColClasses : 0);
 }
-inline int class_rows(int cls) { return cls < kNumTileClass ? kMaxRows : 16 * ((cls - kNumTileClass) / 2 + 1); }
-inline int class_cols(int cls) { return cls < kNumTileClass ? 16 * (cls + 1) : 16 * ((cls - kNumTileClass) % 2 + 1); }
+inline int class_rows(int cls) {
+    return cls < kNumTileClass ? (cls >= kColClasses ? kMaxRows : kShortRows) : 16 * ((cls - kNumTileClass) / 2 + 1);
+}
+inline int class_cols(int cls) {
+    return cls < kNumTileClass ? 16 * (cls % kColClasses + 1) : 16 * ((cls - kNumTileClass) % 2 + 1);
+}
 
 // Records per task that fit the LDS staging of the kernels: a work list
 // whose every task has at most kRecG groups, whose contributions (at most

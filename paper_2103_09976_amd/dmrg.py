@@ -21,7 +21,7 @@ DMRG_LEFT, DMRG_RIGHT = 0, 1
 DMRG_SCHEME_NC, DMRG_SCHEME_CN = 0, 1
 DMRG_F64, DMRG_F32 = 0, 1
 DMRG_PREC_F64, DMRG_PREC_F32 = 0, 1
-DMRG_HEFF_LAUNCHES = 11   # kernel launches of one H_eff product (dmrg_heff_profile)
+DMRG_HEFF_LAUNCHES = 17   # kernel launches of one H_eff product (dmrg_heff_profile)
 
 SITE_Q = ((0, 0), (1, 0), (0, 1), (1, 1))
 
