@@ -226,11 +226,12 @@ def main():
     t0 = time.perf_counter()
     last = None
     for i in range(args.steps):
-        rec, objs = step(recs)
+        # free the previous step's blocks first, so that one step's operators
+        # are resident at a time
         if last is not None:
             for o in last:
                 o.free()
-        last = objs
+        rec, last = step(recs)
         print(f"[bench] step {i} ms_step={rec['ms_step']:.0f} build={rec['ms_build']:.0f} "
               f"davidson={rec['ms_davidson']:.0f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()

@@ -198,13 +198,23 @@ def test_mixed_vs_fp64_energy():
 
 @pytest.mark.parametrize("K,N,M,seed", [(12, 12, None, 81), (14, 14, 1000, 82)])
 def test_large_sector_twins(K, N, M, seed):
-    """Sectors of 100 and 166 rows: the 128- and 320-row kernel classes, FP64 and FP32."""
+    """Sectors of 100 and 166 rows, split into row tiles of <= 96 (96 + 4 and
+    96 + 70): both row buckets of the slice kernel (<= 80 and 81..96 rows) do
+    work, FP64 and FP32."""
+    import torch
+    d = _lib()
     p = synth.make_problem(K, N, 0, M, seed)
     ref = blockops.MiddleHeff(p, "CN").apply(p.psi)
     ctx, L, R, H, keep = _step(p, arena=8 << 30)
     got = _apply(H, p.psi)
-    got32 = _apply(H, p.psi, _lib().DMRG_PREC_F32)
+    got32 = _apply(H, p.psi, d.DMRG_PREC_F32)
+    x = torch.from_numpy(p.psi.copy()).cuda()
+    launches = H.profile(x, torch.empty_like(x))
+    torch.cuda.synchronize()
     _close(H, L, R, ctx)
+    work = {k & 255: fl for k, _, fl in launches}
+    assert any(work[k] > 0 for k in range(0, 6)), work
+    assert any(work[k] > 0 for k in range(6, 12)), work
     e64, e32 = _rel(got, ref), _rel(got32, ref)
     print(f"[gpu] twin K={K} M={M} f64={e64:.2e} f32={e32:.2e}", flush=True)
     assert e64 <= 1e-12
