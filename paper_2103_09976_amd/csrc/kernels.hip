@@ -228,48 +228,59 @@ __global__ __launch_bounds__(256, (SliceOcc<T, RT>::waves)) void slice_kernel(Ba
             const T* Bp = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
-            // the fragment loads of the chunk at k0 (clamped when out of range).
-            // Lane (r, g) takes k = k0 + 4g + s: rows 16i + r of A, column gcol of B.
+            // The chunk at k0: lane (r, g) covers k = k0 + 4g .. k0 + 4g + 3.  In
+            // FP32 with K >= 4 it reads the four k at kb = min(k0 + 4g, K - 4)
+            // instead, which always lie inside the row, so a partial last chunk
+            // uses the same vector loads as a full one; k below k0 + 4g (covered
+            // by the previous lane group) are then dropped by zeroing B.
+            // Otherwise the k past K read offset 0 of the block (FP64 measured
+            // slower with the sliding window).  Rows of A past mu read row 0
+            // (they only reach U rows past mu, zeroed below).
+            const bool slide = sizeof(T) == 4 && K >= 4;
             auto fetch = [&](int k0, T (&fa)[RT][4], T (&fb)[4]) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const int gcol = tk.col0 + 16 * w + lr;
                 const bool colok = 16 * w + lr < ncv;
-                const bool full = k0 + 16 <= K;
+                const int kk = k0 + 4 * lk;
+                const int kb = slide ? min(kk, K - 4) : kk;
+                const bool vec4 = slide || k0 + 16 <= K;   // the four k lie inside the row
 #pragma unroll
                 for (int i = 0; i < RT; ++i) {
                     if (i >= nru) continue;
                     const int row = 16 * i + lr;
                     const bool rok = row < mu;
-                    if (!ta && full) {
-                        ld4_at(Ap, rok ? (uint32_t)(row * lda + k0 + 4 * lk) : 0u, fa[i]);
+                    if (!ta && vec4) {
+                        ld4_at(Ap, rok ? (uint32_t)(row * lda + kb) : 0u, fa[i]);
                     } else {
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
-                            const int k = k0 + 4 * lk + s;
+                            const int k = kb + s;
                             const bool ok = rok && k < K;
                             fa[i][s] = ld_at(Ap, ok ? (ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k)) : 0u);
                         }
                     }
                 }
-                if (tb && full) {
-                    ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + k0 + 4 * lk) : 0u, fb);
+                if (tb && vec4) {
+                    ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + kb) : 0u, fb);
                 } else {
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
-                        const int k = k0 + 4 * lk + s;
+                        const int k = kb + s;
                         const bool ok = colok && k < K;
                         fb[s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gcol * ldb + k) : (uint32_t)(k * ldb + gcol)) : 0u);
                     }
                 }
             };
-            // U += alpha * A . B of the chunk at k0.  k past K or a column past
-            // the tile: B is zeroed (A's clamped rows only reach U rows past mu,
-            // zeroed below).
+            // U += alpha * A . B of the chunk at k0.  B is zeroed at the k this
+            // lane group does not own (below k0 + 4g or past K) and at columns
+            // past the tile.
             auto mmas = [&](int k0, T (&fa)[RT][4], T (&fb)[4]) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const bool colok = 16 * w + lr < ncv;
+                const int kk = k0 + 4 * lk;
+                const int kb = slide ? min(kk, K - 4) : kk;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) fb[s] = (colok && k0 + 4 * lk + s < K) ? alpha * fb[s] : T(0);
+                for (int s = 0; s < 4; ++s) fb[s] = (colok && kb + s >= kk && kb + s < K) ? alpha * fb[s] : T(0);
 #pragma unroll
                 for (int i = 0; i < RT; ++i) {
                     if (i >= nru) continue;
