@@ -229,14 +229,15 @@ __global__ __launch_bounds__(256, (SliceOcc<T, RT>::waves)) void slice_kernel(Ba
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
             // The chunk at k0: lane (r, g) covers k = k0 + 4g .. k0 + 4g + 3.  In
-            // FP32 with K >= 4 it reads the four k at kb = min(k0 + 4g, K - 4)
-            // instead, which always lie inside the row, so a partial last chunk
-            // uses the same vector loads as a full one; k below k0 + 4g (covered
-            // by the previous lane group) are then dropped by zeroing B.
-            // Otherwise the k past K read offset 0 of the block (FP64 measured
-            // slower with the sliding window).  Rows of A past mu read row 0
-            // (they only reach U rows past mu, zeroed below).
-            const bool slide = sizeof(T) == 4 && K >= 4;
+            // FP32 tiles of at most five row tiles, with K >= 4, it reads the four
+            // k at kb = min(k0 + 4g, K - 4) instead, which always lie inside the
+            // row, so a partial last chunk uses the same vector loads as a full
+            // one; k below k0 + 4g (covered by the previous lane group) are then
+            // dropped by zeroing B.  Otherwise the k past K read offset 0 of the
+            // block (FP64 and six-row-tile tiles measured slower with the sliding
+            // window).  Rows of A past mu read row 0 (they only reach U rows past
+            // mu, zeroed below).
+            const bool slide = sizeof(T) == 4 && RT <= 5 && K >= 4;
             auto fetch = [&](int k0, T (&fa)[RT][4], T (&fb)[4]) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const int gcol = tk.col0 + 16 * w + lr;
