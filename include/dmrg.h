@@ -20,8 +20,11 @@
  *                          generated once for each site", Section II.G)
  *   dmrg_heff_apply     -> H_eff psi (Appendix A, effective eigenproblem)
  *   dmrg_davidson       -> Davidson solution of the effective eigenproblem
- *   dmrg_renormalize    -> transformation of the blocked left operators into a
- *                          new renormalized basis (Appendix A)
+ *                          (also one iteration at a time: dmrg_davidson_step)
+ *   dmrg_heff_renormalize, dmrg_renormalize
+ *                       -> transformation of blocked operators into a new
+ *                          renormalized basis (Appendix A)
+ *   dmrg_query_workspace-> arena bytes of each call, host only
  *
  * Conventions shared with every caller:
  *   spin-orbital p = 2*i + s (s = 0 alpha, 1 beta), spatial i = 0..K-1;
@@ -64,7 +67,7 @@ enum {
     DMRG_E_HIP = -4,          /* HIP runtime error */
     DMRG_E_NONFINITE = -5,    /* NaN/Inf met in a Davidson vector */
     DMRG_E_STATE = -6,        /* call out of order (e.g. no integrals) */
-    DMRG_E_UNSUPPORTED = -7   /* a sector larger than the kernels' 320-row limit */
+    DMRG_E_UNSUPPORTED = -7   /* a size the kernels cannot address (an operand of 2^32 bytes or more) */
 };
 
 enum { DMRG_LEFT = 0, DMRG_RIGHT = 1 };
@@ -154,35 +157,125 @@ dmrg_status dmrg_build_block(dmrg_ctx* ctx, int32_t side, int32_t n_sites,
  * spin-orbitals to its left.  In place; cost O(K^4 M^2). */
 dmrg_status dmrg_normal_to_complementary(dmrg_ctx* ctx, dmrg_opset* right, void* stream);
 
+/* Layout of the two-site wavefunction in a caller's vector: one entry per
+ * sub-block (a, s1, s2, b) -- left-block sector a = qn_left[2i..2i+1], dot
+ * states s1 = site1[i], s2 = site2[i] (0..3 = |0>,|a>,|b>,|ab>); the right
+ * sector b completes the target and the sub-block is m_a x m_b row-major at
+ * element offset[i].  Every valid (a, s1, s2) must appear exactly once and
+ * the sub-blocks must tile [0, dim) without gaps or overlaps (dim = the sum
+ * of m_a m_b).  Host arrays, copied by the library. */
+typedef struct {
+    int32_t n_blocks;
+    const int32_t* qn_left;
+    const int32_t* site1;
+    const int32_t* site2;
+    const int64_t* offset;
+} dmrg_psi_layout;
+
 /* Blocking of the dots d1 (onto the left block) and d2 (onto the right
  * block, which must hold complementary operators) and the work list of
- * H_eff = sum over NC terms X^{L'} (x) Y^{R'}; built once, reused by every
- * product.  n_roots sets the batch the FP32 copies and work lists serve. */
+ * H_eff = sum over NC terms X^{L'} (x) Y^{R'} (Appendix A, effective
+ * eigenproblem; Section II.G: the list of GEMMs is generated once for each
+ * site and reused by every product).
+ *   layout:    wavefunction layout of psi / sigma, or NULL for the default
+ *              order (Lb sector a, then s1, then s2; contiguous);
+ *   n_roots:   the largest vector batch one product serves at once (the
+ *              partial-tile buffer is sized for it);
+ *   precision: DMRG_PREC_F64 -- FP64 products only; DMRG_PREC_F32 -- FP32
+ *              products as well (the FP32-mixed policy): the operators are
+ *              rounded to binary32 copies here, once.
+ * DMRG_E_ARG for a layout that does not match the blocks; DMRG_E_WORKSPACE if
+ * the arena cannot hold the blocked operators, lists and copies. */
 dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right,
-                             int32_t n_roots, dmrg_heff** out, void* stream);
+                             const dmrg_psi_layout* layout, int32_t n_roots, int32_t precision,
+                             dmrg_heff** out, void* stream);
 int64_t dmrg_heff_dim(const dmrg_heff* H);
+/* Readback of the layout in use (host arrays of capacity >= n, any may be
+ * NULL): qn_left / qn_right [2 n], site1 / site2 [n], rows / cols / offset
+ * [n].  Returns the number of sub-blocks. */
+int32_t dmrg_heff_psi_layout(const dmrg_heff* H, int32_t n, int32_t* qn_left, int32_t* site1, int32_t* site2,
+                             int32_t* qn_right, int64_t* rows, int64_t* cols, int64_t* offset);
 
 /* sigma = H_eff psi for n_vec vectors (overwrite).  precision DMRG_PREC_F64:
  * psi, sigma are double; DMRG_PREC_F32: float (operators rounded to binary32
- * once, FP32 products with FP32 accumulation). */
+ * once, FP32 products with FP32 accumulation; DMRG_E_STATE if H was created
+ * for FP64 only).  Vectors run in batches of n_roots. */
 dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec,
                             const void* psi, void* sigma, void* stream);
 
 /* diag[dim] (device, double) = diagonal of H_eff (Davidson preconditioner). */
 dmrg_status dmrg_heff_diag(dmrg_heff* H, double* diag, void* stream);
 
-/* Block Davidson for the n_roots lowest eigenpairs.  psi_io[n_roots*dim]
- * (device, double): start vectors in, Ritz vectors out.  energies[n_roots]
- * host out (e_core included).  Non-convergence is reported in stats, not as
- * an error. */
+/* Block Davidson for the n_roots lowest eigenpairs of the effective
+ * eigenproblem (Appendix A; the paper solves it with Davidson's method).
+ * psi_io[n_roots*dim] (device, double): start vectors in, Ritz vectors out.
+ * energies[n_roots] host out (e_core included).  Non-convergence is reported
+ * in stats, not as an error; DMRG_E_NONFINITE on NaN/Inf in a product. */
 dmrg_status dmrg_davidson(dmrg_heff* H, int32_t n_roots, double* psi_io, double* energies,
                           const dmrg_dav_opts* opts, dmrg_dav_stats* stats, void* stream);
 
-/* Transformation of the blocked L' = Lb + d1 operators through the isometry
- * adding d1 (Appendix A, operator transformation): returns the left block of
- * sites [0, KL+1) in the new renormalized basis. */
-dmrg_status dmrg_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_opset** out,
+/* The same solve one iteration at a time (dmrg_davidson is start, step until
+ * done, finish).  start: workspace from the arena, start block psi0 (device,
+ * not modified) orthonormalised, first products and Rayleigh-Ritz.  step:
+ * one iteration (corrections and their products, or a restart; then
+ * Rayleigh-Ritz); *done = 1 once converged, at max_iter / fixed_iters, or
+ * when no new direction remains (further steps do nothing); energies
+ * [n_roots] (host, optional) receive the current Ritz values and
+ * *max_residual (optional) the largest residual norm.  finish: final
+ * energies (FP64 Rayleigh quotients when FP32 products were used), Ritz
+ * vectors to psi_out[n_roots*dim] (device) and stats.  free releases the
+ * workspace (also after a failed call). */
+typedef struct dmrg_dav dmrg_dav;
+dmrg_status dmrg_davidson_start(dmrg_heff* H, int32_t n_roots, const double* psi0, const dmrg_dav_opts* opts,
+                                dmrg_dav** out, void* stream);
+dmrg_status dmrg_davidson_step(dmrg_dav* D, int32_t* done, double* energies, double* max_residual);
+dmrg_status dmrg_davidson_finish(dmrg_dav* D, double* psi_out, double* energies, dmrg_dav_stats* stats);
+void dmrg_davidson_free(dmrg_dav* D);
+
+/* Transformation of the blocked L' = Lb + d1 operators of H through the
+ * isometry adding d1 (Appendix A, operator transformation): returns the left
+ * block of sites [0, KL+1) in the new renormalized basis.  Reuses the
+ * delayed L' operators and integral-weighted sums H already holds. */
+dmrg_status dmrg_heff_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_opset** out,
+                                  void* stream);
+
+/* One blocking + transformation step of any block (Appendix A, blocking
+ * formula then operator transformation): `in` grown by its next site (a left
+ * block of n sites by site n, a right block of n sites by site K-1-n) and
+ * transformed through `isometry` (the MPS tensor of that site; rows in the
+ * enlarged order, see the conventions above).  The result holds the same
+ * kinds of operators as `in` (normal, or complementary for an NC right
+ * block) for the grown block; `in` is left unchanged.  DMRG_E_ARG if the
+ * isometry's rows do not match the enlarged sectors. */
+dmrg_status dmrg_renormalize(dmrg_ctx* ctx, const dmrg_opset* in, const dmrg_bsm* isometry, dmrg_opset** out,
                              void* stream);
+
+/* Arena bytes a call needs (free, beyond what is in use), computed on the
+ * host without device work.  what / args:
+ *   DMRG_WS_BLOCK       dmrg_ws_block: dmrg_build_block from the vacuum;
+ *                       the isometries' metadata only (data may be NULL).
+ *                       ctx may be NULL: then K, n_elec, two_sz and the share
+ *                       (n_proc, proc_id) come from the args and every
+ *                       integral is taken as nonzero (an upper bound);
+ *   DMRG_WS_TRANSFORM   dmrg_ws_transform: dmrg_normal_to_complementary;
+ *   DMRG_WS_HEFF        dmrg_ws_heff: dmrg_heff_create (default layout);
+ *   DMRG_WS_DAVIDSON    dmrg_ws_davidson: dmrg_davidson(_start); ctx may
+ *                       be NULL;
+ *   DMRG_WS_RENORMALIZE dmrg_ws_renorm: dmrg_renormalize.
+ * The build figures are the peak of the smallest batches the build can run
+ * in (larger arenas run larger batches); the result of the call (an operator
+ * set, an H_eff) is included and stays in the arena afterwards. */
+enum { DMRG_WS_BLOCK = 0, DMRG_WS_TRANSFORM = 1, DMRG_WS_HEFF = 2, DMRG_WS_DAVIDSON = 3, DMRG_WS_RENORMALIZE = 4 };
+typedef struct {
+    int32_t K, n_elec, two_sz, n_proc, proc_id;   /* used when ctx is NULL */
+    int32_t side, n_sites, scheme;
+    const dmrg_bsm* isometries;
+} dmrg_ws_block;
+typedef struct { const dmrg_opset* right; } dmrg_ws_transform;
+typedef struct { const dmrg_opset* left; const dmrg_opset* right; int32_t n_roots, precision; } dmrg_ws_heff;
+typedef struct { int64_t dim; int32_t n_roots; dmrg_dav_opts opts; } dmrg_ws_davidson;
+typedef struct { const dmrg_opset* in; const dmrg_bsm* isometry; } dmrg_ws_renorm;
+dmrg_status dmrg_query_workspace(const dmrg_ctx* ctx, int32_t what, const void* args, int64_t* bytes);
 
 /* Algorithmic flops of one H_eff psi per vector (sum over terms of the
  * cheaper multiplication order; identity and scalar factors cost 0), and the
@@ -199,11 +292,12 @@ int32_t dmrg_heff_terms(const dmrg_heff* H, int32_t* n2, int32_t* n1, int32_t* n
  * 2*mu*k*cols per A.B, padding and identities excluded), kind[i] = kernel
  * kind in bits 0-7 (0..5: slice kernel, tiles of 1..6 16-column slices and
  * at most 80 rows; 6..11: the same with at most 96 rows; 12..15: one-wave
- * kernel with (rows, cols) tiles of (16,16), (16,32), (32,16), (32,32); 16:
+ * kernel with (rows, cols) tiles of (16,16), (16,32), (32,16), (32,32);
+ * 16..21: tall kernel, tiles of 1..6 slices with 97..320 rows; 22:
  * partial-tile reduction) | 256 when the task records are staged in LDS.
  * Launches with no work report ms = 0.  Synchronizes `stream`.
  * Returns the number of launches (>= 0) or a negative dmrg_status. */
-#define DMRG_HEFF_LAUNCHES 17
+#define DMRG_HEFF_LAUNCHES 23
 int32_t dmrg_heff_profile(dmrg_heff* H, int32_t precision, const void* psi, void* sigma, int32_t n, float* ms,
                           double* flops, int32_t* kind, void* stream);
 

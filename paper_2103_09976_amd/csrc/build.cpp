@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <tuple>
 
@@ -405,11 +406,30 @@ static dmrg_status layout_new_set(Ctx* C, const Iso& iso, const Grown& G, OpSetI
     return alloc_set(C, nw);
 }
 
-// transformation of the grown operators i0..i1-1 into their rows of nw
-static dmrg_status renormalize_range(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const Iso& iso,
-                                     const Grown& G, size_t i0, size_t i1, OpSetImpl& nw, void* stream) {
+// Rows of a new-basis block above which its transformation runs in two
+// passes (DMRG_TWO_PASS_ROWS overrides; a GPU test lowers it).
+static int two_pass_rows() {
+    const char* e = std::getenv("DMRG_TWO_PASS_ROWS");
+    return e ? std::max(1, std::atoi(e)) : dmrgk::kTallRows;
+}
+
+// Transformation of grown operators i0..i1-1 into their rows of nw:
+//   O_new[q' <- q] = sum_{s'} U_{q',s'}^T T_{s'},  T_{s'} = sum_{s, k} c_k Z_k U_{q,s}
+// (Appendix A, operator transformation, with the blocked operator kept as its
+// site transitions (s', s) and old-block components Z_k).  A block whose new
+// bra dimension fits the tall tile runs in one pass: T stays in registers /
+// LDS and U^T T follows at once.  A taller block would recompute T for every
+// row tile of the output, so it runs in two: T_{s'} is first formed in a
+// temporary buffer (buffer 4), then U^T T is a plain product of it.  The
+// operators are taken in sub-ranges whose temporaries stay below
+// kGrowBatchBytes.
+static dmrg_status renormalize_sub(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const Iso& iso,
+                                   const Grown& G, size_t i0, size_t i1, OpSetImpl& nw, int two_rows,
+                                   void* stream) {
     dmrg_status st = DMRG_OK;
-    WorkList wl;
+    const double t0 = wall_s();
+    WorkList wl, wl1;   // wl1: first pass of the two-pass blocks (into the temporaries)
+    int64_t toff = 0;   // elements of the temporaries
     const Basis& ob = old.basis;
     const Basis& nb = nw.basis;
     for (size_t i = i0; i < i1; ++i) {
@@ -422,21 +442,14 @@ static dmrg_status renormalize_range(Ctx* C, const OpSetImpl& old, const OpSetIm
         for (size_t b = 0; b < S.ket.size(); ++b) {
             const int kq = S.ket[b], kb = S.bra[b];
             const int mq = nb.m[kq], mqb = nb.m[kb];
+            const bool two = mqb > two_rows;
             const int g0 = (int)wl.groups.size();
-            for (auto& kv : bucket) {
-                const int sb = kv.first.first, sk = kv.first.second;
+            // contributions of bucket (sb, sk): sum_k c_k Z_k U_{q,sk} (the A.B products of T_sb)
+            auto add_contribs = [&](WorkList& w, int sb, int sk, const std::vector<int>& comps) {
                 const int a = ob.find(nb.q[kq] - kSiteQ[sk]);
                 const int a2 = ob.find(nb.q[kb] - kSiteQ[sb]);
-                if (a < 0 || a2 < 0) continue;
-                dmrgk::Group g{};
-                g.x_off = iso.off[kb] + (int64_t)iso.seg[kb][sb] * mqb;
-                g.ldx = mqb;
-                g.mu = ob.m[a2];
-                g.x_coef = 1.0;
-                g.xid_coef = 0.0;
-                g.flags = 2 | dmrgk::G_TRANS_X | dmrgk::G_HAS_X;
-                g.c0 = (int)wl.contribs.size();
-                for (int ci : kv.second) {
+                if (a < 0 || a2 < 0) return;
+                for (int ci : comps) {
                     const Comp& cp = T.comps[ci];
                     const double sg = (cp.sgn_par && (ob.q[a].n() & 1)) ? -1.0 : 1.0;
                     dmrgk::Contrib c{};
@@ -457,10 +470,59 @@ static dmrg_status renormalize_range(Ctx* C, const OpSetImpl& old, const OpSetIm
                         c.lda = ld;
                         c.flags = abuf | (2 << 3) | (tr ? dmrgk::F_TRANS_A : 0);
                     }
-                    wl.contribs.push_back(c);
+                    w.contribs.push_back(c);
                 }
-                g.c1 = (int)wl.contribs.size();
-                if (g.c1 > g.c0) wl.groups.push_back(g);
+            };
+            if (!two) {
+                for (auto& kv : bucket) {
+                    const int sb = kv.first.first;
+                    const int a2 = ob.find(nb.q[kb] - kSiteQ[sb]);
+                    if (a2 < 0 || ob.find(nb.q[kq] - kSiteQ[kv.first.second]) < 0) continue;
+                    dmrgk::Group g{};
+                    g.x_off = iso.off[kb] + (int64_t)iso.seg[kb][sb] * mqb;
+                    g.ldx = mqb;
+                    g.mu = ob.m[a2];
+                    g.x_coef = 1.0;
+                    g.flags = 2 | dmrgk::G_TRANS_X | dmrgk::G_HAS_X;
+                    g.c0 = (int)wl.contribs.size();
+                    add_contribs(wl, sb, kv.first.second, kv.second);
+                    g.c1 = (int)wl.contribs.size();
+                    if (g.c1 > g.c0) wl.groups.push_back(g);
+                }
+            } else {
+                for (int sb = 0; sb < 4; ++sb) {
+                    const int a2 = ob.find(nb.q[kb] - kSiteQ[sb]);
+                    if (a2 < 0) continue;
+                    // first pass: T_sb = sum over the buckets (sb, *) into the temporaries
+                    dmrgk::Group g1{};
+                    g1.xid_coef = 1.0;
+                    g1.mu = ob.m[a2];
+                    g1.c0 = (int)wl1.contribs.size();
+                    for (auto& kv : bucket)
+                        if (kv.first.first == sb) add_contribs(wl1, sb, kv.first.second, kv.second);
+                    g1.c1 = (int)wl1.contribs.size();
+                    if (g1.c1 == g1.c0) continue;
+                    const int gi = (int)wl1.groups.size();
+                    wl1.groups.push_back(g1);
+                    emit_block_tasks(wl1, 4, toff, mq, ob.m[a2], mq, gi, gi + 1);
+                    // second pass: O_new += U_{q',sb}^T T_sb
+                    dmrgk::Group g{};
+                    g.x_off = iso.off[kb] + (int64_t)iso.seg[kb][sb] * mqb;
+                    g.ldx = mqb;
+                    g.mu = ob.m[a2];
+                    g.x_coef = 1.0;
+                    g.flags = 2 | dmrgk::G_TRANS_X | dmrgk::G_HAS_X;
+                    g.c0 = (int)wl.contribs.size();
+                    dmrgk::Contrib c{};
+                    c.a_off = toff;
+                    c.lda = mq;
+                    c.alpha = 1.0;
+                    c.flags = 4 | dmrgk::F_ID_B;
+                    wl.contribs.push_back(c);
+                    g.c1 = (int)wl.contribs.size();
+                    wl.groups.push_back(g);
+                    toff += (int64_t)ob.m[a2] * mq;
+                }
             }
             emit_block_tasks(wl, 3, F.base + (int64_t)fi.second * F.stride + S.off[b], mq, mqb, mq, g0,
                              (int)wl.groups.size());
@@ -473,28 +535,82 @@ static dmrg_status renormalize_range(Ctx* C, const OpSetImpl& old, const OpSetIm
     for (size_t i = 0; i < iso.off.size(); ++i)
         sz[2] = std::max<int64_t>(sz[2], iso.off[i] + (int64_t)iso.d[i] * iso.nb.m[i]);
     sz[3] = nw.elems;
-    DevWork dw;
+    sz[4] = toff;
+    int64_t treg = -1;
+    if (toff > 0) {
+        treg = C->arena.alloc(toff * 8);
+        if (treg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for transformation temporaries");
+    }
+    DevWork dw, dw1;
     st = validate_work(wl, sz);
+    if (st == DMRG_OK && toff > 0) st = validate_work(wl1, sz);
+    if (st == DMRG_OK && toff > 0) st = upload_work(C, wl1, dw1, stream);
     if (st == DMRG_OK) st = upload_work(C, wl, dw, stream);
-    if (st != DMRG_OK) return st;
+    const double t1 = wall_s();
+    C->tm[TM_REN_HOST] += t1 - t0;
     dmrgk::Bases<double> bs{};
     bs.p[0] = old.dev;
     bs.p[1] = temps ? temps->dev : old.dev;
     bs.p[2] = const_cast<double*>(iso.dev);
     bs.p[3] = nw.dev;
-    st = run_work_f64(dw, bs, 1, stream);
-    if (st == DMRG_OK) {
-        const int e = (int)hipStreamSynchronize((hipStream_t)stream);
-        if (e) st = hip_fail(e, "renormalization");
+    bs.p[4] = treg >= 0 ? (double*)(C->arena.base + treg) : old.dev;
+    if (st == DMRG_OK && !C->dry) {
+        if (toff > 0) st = run_work_f64(dw1, bs, 1, stream);
+        if (st == DMRG_OK) st = run_work_f64(dw, bs, 1, stream);
+        if (st == DMRG_OK) {
+            const int e = (int)hipStreamSynchronize((hipStream_t)stream);
+            if (e) st = hip_fail(e, "renormalization");
+        }
     }
     free_work(C, dw);
+    free_work(C, dw1);
+    if (treg >= 0) C->arena.release(treg);
+    C->tm[TM_REN_DEV] += wall_s() - t1;
     return st;
+}
+
+// temporaries (elements) of the two-pass blocks of grown operator i
+static int64_t two_pass_elems(const OpSetImpl& old, const Grown& G, size_t i, const OpSetImpl& nw, int two_rows) {
+    const auto fi = nw.lookup.at(G.keys[i]);
+    const Skel& S = nw.skels[nw.fams[fi.first].skel];
+    const Basis& ob = old.basis;
+    const Basis& nb = nw.basis;
+    int64_t e = 0;
+    for (size_t b = 0; b < S.ket.size(); ++b) {
+        const int kq = S.ket[b], kb = S.bra[b];
+        if (nb.m[kb] <= two_rows) continue;
+        for (int sb = 0; sb < 4; ++sb) {
+            const int a2 = ob.find(nb.q[kb] - kSiteQ[sb]);
+            if (a2 >= 0) e += (int64_t)ob.m[a2] * nb.m[kq];
+        }
+    }
+    return e;
+}
+
+static dmrg_status renormalize_range(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const Iso& iso,
+                                     const Grown& G, size_t i0, size_t i1, OpSetImpl& nw, void* stream) {
+    const int two_rows = two_pass_rows();
+    size_t a = i0;
+    while (a < i1) {
+        size_t b = a;
+        int64_t e = 0;
+        while (b < i1) {
+            const int64_t x = two_pass_elems(old, G, b, nw, two_rows);
+            if (b > a && (e + x) * 8 > kGrowBatchBytes) break;
+            e += x;
+            ++b;
+        }
+        dmrg_status st = renormalize_sub(C, old, temps, iso, G, a, b, nw, two_rows, stream);
+        if (st != DMRG_OK) return st;
+        a = b;
+    }
+    return DMRG_OK;
 }
 
 dmrg_status renormalize_grown(Ctx* C, const OpSetImpl& old, const OpSetImpl* temps, const dmrg_bsm* iso_desc,
                               const Grown& G, OpSetImpl& nw, void* stream) {
     Iso iso;
-    dmrg_status st = make_iso(old.basis, iso_desc, iso);
+    dmrg_status st = make_iso(old.basis, iso_desc, iso, !C->dry);
     if (st == DMRG_OK) st = layout_new_set(C, iso, G, nw);
     if (st == DMRG_OK) st = renormalize_range(C, old, temps, iso, G, 0, G.ops.size(), nw, stream);
     return st;
@@ -506,17 +622,21 @@ dmrg_status renormalize_grown(Ctx* C, const OpSetImpl& old, const OpSetImpl* tem
 // the transient memory stays bounded when thousands of operators grow at once.
 dmrg_status grow_and_renormalize(Ctx* C, OpSetImpl& old, Grown& G, const dmrg_bsm* iso_desc,
                                  OpSetImpl& nw, void* stream) {
+    const double t0 = wall_s();
     WSumPlan plan;
     std::vector<int> rb;
     compact(G.ops, old, plan, &rb);
     Iso iso;
-    dmrg_status st = make_iso(old.basis, iso_desc, iso);
+    dmrg_status st = make_iso(old.basis, iso_desc, iso, !C->dry);
     if (st == DMRG_OK) st = layout_new_set(C, iso, G, nw);
     if (st != DMRG_OK) return st;
-    // DMRG_GROW_BATCH_BYTES overrides the budget (tests use it to force small batches)
+    C->tm[TM_PLAN] += wall_s() - t0;
+    // The budget is a fixed size, not a share of the free arena, so that the
+    // sequence of allocations does not depend on the arena's size and a dry
+    // run (dmrg_query_workspace) reproduces it exactly.  DMRG_GROW_BATCH_BYTES
+    // overrides it (a GPU test sets 1: one operator's temporaries at a time).
     const char* env = std::getenv("DMRG_GROW_BATCH_BYTES");
-    const int64_t budget = env ? std::atoll(env)
-                               : std::max<int64_t>(int64_t(1) << 28, (C->arena.bytes - C->arena.used) / 2);
+    const int64_t budget = env ? std::atoll(env) : kGrowBatchBytes;
     const size_t n = G.ops.size();
     size_t i0 = 0;
     while (i0 < n && st == DMRG_OK) {
@@ -547,6 +667,52 @@ dmrg_status grow_and_renormalize(Ctx* C, OpSetImpl& old, Grown& G, const dmrg_bs
     return st;
 }
 
+// The operators of block `cur` grown by its next site, in transition form
+// (left block of n sites: site n, with R_p kept for every p to its right;
+// right block of n sites: site K-1-n, with R_p, P, Q for every p to its left).
+static void grow_ops(const Ctx* C, const OpSetImpl& cur, Grown& G) {
+    const int K = C->K;
+    if (cur.side == DMRG_LEFT) {
+        const int n = cur.nsites;
+        std::vector<int> outside;
+        for (int p = 2 * (n + 1); p < 2 * K; ++p) outside.push_back(p);
+        grow_left(C, cur, n, outside, G);
+    } else {
+        const int n = K - 1 - cur.nsites;
+        std::vector<int> before;
+        for (int p = 0; p < 2 * n; ++p) before.push_back(p);
+        if (cur.kind == 1) grow_right_compl(C, cur, n, before, G);
+        else grow_right_normal(C, cur, n, before, G);
+    }
+}
+
+// spin-orbitals and site count of the grown block
+static void grown_meta(const Ctx* C, const OpSetImpl& cur, OpSetImpl& nw) {
+    nw.side = cur.side;
+    nw.kind = cur.kind;
+    nw.nsites = cur.nsites + 1;
+    if (cur.side == DMRG_LEFT) {
+        const int n = cur.nsites;
+        nw.orbs = cur.orbs;
+        nw.orbs.push_back(2 * n);
+        nw.orbs.push_back(2 * n + 1);
+    } else {
+        const int n = C->K - 1 - cur.nsites;
+        nw.orbs = {2 * n, 2 * n + 1};
+        nw.orbs.insert(nw.orbs.end(), cur.orbs.begin(), cur.orbs.end());
+    }
+}
+
+// One blocking + transformation step: cur grown by its next site through iso.
+static dmrg_status grow_step(Ctx* C, OpSetImpl& cur, const dmrg_bsm* iso, OpSetImpl& nw, void* stream) {
+    Grown G;
+    const double tg = wall_s();
+    grow_ops(C, cur, G);
+    C->tm[TM_GROW] += wall_s() - tg;
+    grown_meta(C, cur, nw);
+    return grow_and_renormalize(C, cur, G, iso, nw, stream);
+}
+
 static dmrg_status vacuum(Ctx* C, OpSetImpl& S, int side, int kind, void* stream) {
     S = OpSetImpl();
     S.basis.q = {QN(0, 0)};
@@ -567,7 +733,7 @@ static dmrg_status vacuum(Ctx* C, OpSetImpl& S, int side, int kind, void* stream
     }
     dmrg_status st = alloc_set(C, S);
     if (st != DMRG_OK) return st;
-    DMRG_HIP(hipMemsetAsync(S.dev, 0, (size_t)std::max<int64_t>(S.elems, 1) * 8, (hipStream_t)stream));
+    if (!C->dry) DMRG_HIP(hipMemsetAsync(S.dev, 0, (size_t)std::max<int64_t>(S.elems, 1) * 8, (hipStream_t)stream));
     return DMRG_OK;
 }
 
@@ -618,6 +784,27 @@ static int proc2(int p, int i, int j, int P) {
     return ((x % P) + P) % P == 0;
 }
 
+// Sub-Hamiltonian proc_id (1-based) of n_proc with the NC assignment
+// (Section II.B): t_ij scaled by [proc(p,i) + proc(p,j)] / 2, v_ijkl kept when
+// the sorted tuple is owned (proc(p, j) if j = k, else proc(p, i, j)).
+static void apply_share_mask(Ctx* ctx) {
+    const int K = ctx->K, n_proc = ctx->n_proc, proc_id = ctx->proc_id;
+    if (n_proc <= 1) return;
+    const size_t K1 = K;
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j)
+            ctx->h[i * K1 + j] *= 0.5 * (proc1(proc_id, i + 1, n_proc) + proc1(proc_id, j + 1, n_proc));
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j)
+            for (int k = 0; k < K; ++k)
+                for (int l = 0; l < K; ++l) {
+                    int s[4] = {i + 1, j + 1, k + 1, l + 1};
+                    std::sort(s, s + 4);
+                    const int own = (s[1] == s[2]) ? proc1(proc_id, s[1], n_proc) : proc2(proc_id, s[0], s[1], n_proc);
+                    if (!own) ctx->g[((i * K1 + j) * K1 + k) * K1 + l] = 0.0;
+                }
+}
+
 dmrg_status dmrg_set_integrals(dmrg_ctx* ctx, int32_t K, int32_t n_elec, int32_t two_sz, const double* h1e,
                                const double* g2e, double e_core, int32_t n_proc, int32_t proc_id) {
     if (!ctx || !h1e || !g2e) return fail(DMRG_E_ARG, "null argument");
@@ -648,22 +835,7 @@ dmrg_status dmrg_set_integrals(dmrg_ctx* ctx, int32_t K, int32_t n_elec, int32_t
     ctx->proc_id = proc_id;
     ctx->h.assign(h1e, h1e + K1 * K1);
     ctx->g.assign(g2e, g2e + K1 * K1 * K1 * K1);
-    if (n_proc > 1) {
-        // sub-Hamiltonian proc_id (1-based), NC assignment
-        for (int i = 0; i < K; ++i)
-            for (int j = 0; j < K; ++j)
-                ctx->h[i * K1 + j] *= 0.5 * (proc1(proc_id, i + 1, n_proc) + proc1(proc_id, j + 1, n_proc));
-        for (int i = 0; i < K; ++i)
-            for (int j = 0; j < K; ++j)
-                for (int k = 0; k < K; ++k)
-                    for (int l = 0; l < K; ++l) {
-                        int s[4] = {i + 1, j + 1, k + 1, l + 1};
-                        std::sort(s, s + 4);
-                        const int own = (s[1] == s[2]) ? proc1(proc_id, s[1], n_proc)
-                                                       : proc2(proc_id, s[0], s[1], n_proc);
-                        if (!own) ctx->g[((i * K1 + j) * K1 + k) * K1 + l] = 0.0;
-                    }
-    }
+    apply_share_mask(ctx);
     ctx->has_ints = true;
     return DMRG_OK;
 }
@@ -680,46 +852,24 @@ dmrg_status dmrg_build_block(dmrg_ctx* ctx, int32_t side, int32_t n_sites, const
     OpSetImpl cur;
     dmrg_status st = vacuum(ctx, cur, side, kind, stream);
     if (st != DMRG_OK) return st;
-    const int K = ctx->K;
+    for (int m = 0; m < TM_N; ++m) ctx->tm[m] = 0.0;
     for (int j = 0; j < n_sites; ++j) {
-        Grown G;
-        if (side == DMRG_LEFT) {
-            const int n = j;
-            std::vector<int> outside;
-            for (int p = 2 * (n + 1); p < 2 * K; ++p) outside.push_back(p);
-            grow_left(ctx, cur, n, outside, G);
-        } else {
-            const int n = K - 1 - j;
-            std::vector<int> before;
-            for (int p = 0; p < 2 * n; ++p) before.push_back(p);
-            if (kind == 1) grow_right_compl(ctx, cur, n, before, G);
-            else grow_right_normal(ctx, cur, n, before, G);
-        }
         OpSetImpl nw;
-        nw.side = side;
-        nw.kind = kind;
-        st = grow_and_renormalize(ctx, cur, G, &isometries[j], nw, stream);
+        st = grow_step(ctx, cur, &isometries[j], nw, stream);
         if (st != DMRG_OK) {
             free_set(ctx, cur);
             free_set(ctx, nw);
             return st;
         }
-        if (side == DMRG_LEFT) {
-            nw.orbs = cur.orbs;
-            nw.orbs.push_back(2 * j);
-            nw.orbs.push_back(2 * j + 1);
-        } else {
-            const int n = K - 1 - j;
-            nw.orbs = {2 * n, 2 * n + 1};
-            nw.orbs.insert(nw.orbs.end(), cur.orbs.begin(), cur.orbs.end());
-        }
-        nw.nsites = j + 1;
         if (std::getenv("DMRG_VERBOSE")) {
             size_t nops = 0;
             for (auto& F : nw.fams) nops += F.keys.size();
-            std::fprintf(stderr, "[dmrg] %s site %d: M=%lld sectors=%d ops=%zu set=%.2f GB arena=%.2f GB peak=%.2f GB\n",
+            std::fprintf(stderr, "[dmrg] %s site %d: M=%lld sectors=%d ops=%zu set=%.2f GB arena=%.2f GB peak=%.2f GB"
+                                 " | cumulative s: grow %.2f plan %.2f wsum host %.2f dev %.2f renorm host %.2f dev %.2f\n",
                          side == DMRG_LEFT ? "left" : "right", j, (long long)nw.basis.total, nw.basis.size(), nops,
-                         nw.elems * 8.0 / 1e9, ctx->arena.used / 1e9, ctx->arena.peak / 1e9);
+                         nw.elems * 8.0 / 1e9, ctx->arena.used / 1e9, ctx->arena.peak / 1e9, ctx->tm[TM_GROW],
+                         ctx->tm[TM_PLAN], ctx->tm[TM_WSUM_HOST], ctx->tm[TM_WSUM_DEV], ctx->tm[TM_REN_HOST],
+                         ctx->tm[TM_REN_DEV]);
         }
         free_set(ctx, cur);
         cur = std::move(nw);
@@ -772,7 +922,7 @@ dmrg_status dmrg_normal_to_complementary(dmrg_ctx* ctx, dmrg_opset* right, void*
             free_set(ctx, nw);
             return fail(DMRG_E_STATE, "family copy mismatch");
         }
-        if (A.stride * (int64_t)A.keys.size() > 0)
+        if (A.stride * (int64_t)A.keys.size() > 0 && !ctx->dry)
             DMRG_HIP(hipMemcpyAsync(nw.dev + B.base, right->dev + A.base, A.stride * A.keys.size() * 8,
                                     hipMemcpyDeviceToDevice, s));
     }
@@ -784,7 +934,7 @@ dmrg_status dmrg_normal_to_complementary(dmrg_ctx* ctx, dmrg_opset* right, void*
         for (size_t g = 0; g < right->fams.size(); ++g)
             if (right->fams[g].kind == in_kind && right->fams[g].dq == D.dq) sf = (int)g;
         if (sf < 0) {
-            if (D.stride * (int64_t)D.keys.size() > 0)
+            if (D.stride * (int64_t)D.keys.size() > 0 && !ctx->dry)
                 DMRG_HIP(hipMemsetAsync(nw.dev + D.base, 0, D.stride * D.keys.size() * 8, s));
             continue;
         }
@@ -805,10 +955,157 @@ dmrg_status dmrg_normal_to_complementary(dmrg_ctx* ctx, dmrg_opset* right, void*
             return st;
         }
     }
-    const int e = (int)hipStreamSynchronize(s);
+    const int e = ctx->dry ? 0 : (int)hipStreamSynchronize(s);
     if (e) return hip_fail(e, "middle transform");
     free_set(ctx, *right);
     static_cast<OpSetImpl&>(*right) = std::move(nw);
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_renormalize(dmrg_ctx* ctx, const dmrg_opset* in, const dmrg_bsm* isometry, dmrg_opset** out,
+                             void* stream) {
+    if (!ctx || !in || !isometry || !out) return fail(DMRG_E_ARG, "null argument");
+    *out = nullptr;
+    if (!ctx->has_ints) return fail(DMRG_E_STATE, "integrals not set");
+    if (in->ctx != ctx) return fail(DMRG_E_ARG, "operator set of another context");
+    if (in->kind != 0 && in->kind != 1) return fail(DMRG_E_ARG, "not a block operator set");
+    if (in->nsites + 1 > ctx->K - 2) return fail(DMRG_E_ARG, "the block cannot grow past the two dots");
+    OpSetImpl& cur = const_cast<dmrg_opset&>(*in);   // read only: the grown operators refer to it
+    OpSetImpl nw;
+    dmrg_status st = grow_step(ctx, cur, isometry, nw, stream);
+    if (st != DMRG_OK) {
+        free_set(ctx, nw);
+        return st;
+    }
+    dmrg_opset* o = new dmrg_opset();
+    static_cast<OpSetImpl&>(*o) = std::move(nw);
+    o->ctx = ctx;
+    *out = o;
+    return DMRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace queries: the call itself, run dry (arena bookkeeping only, no
+// device work) on the context's arena, whose state is restored afterwards
+namespace {
+struct DryScope {
+    Ctx* C;
+    Arena saved;
+    bool was;
+    explicit DryScope(Ctx* c) : C(c), saved(c->arena), was(c->dry) {
+        C->dry = true;
+        Arena& A = C->arena;
+        const int64_t huge = int64_t(1) << 60;
+        // the tail of the arena becomes unbounded, so every allocation succeeds
+        int64_t tail = A.bytes;
+        auto it = A.free_.empty() ? A.free_.end() : std::prev(A.free_.end());
+        if (it != A.free_.end() && it->first + it->second == A.bytes) {
+            tail = it->first;
+            A.free_.erase(it);
+        }
+        A.free_[tail] = huge - tail;
+        A.bytes = huge;
+        A.high = 0;
+        for (auto& kv : A.live_) A.high = std::max(A.high, kv.first + kv.second);
+    }
+    ~DryScope() {
+        C->arena = saved;
+        C->dry = was;
+    }
+};
+
+// generic nonzero integrals for a sizing run without a context: h_ij = x_i +
+// x_j, g_ijkl = (x_i + x_j)(x_k + x_l), 8-fold symmetric, with no
+// cancellation among the integral combinations the operators use
+void generic_integrals(Ctx& c) {
+    const int K = c.K;
+    std::vector<double> x(K);
+    for (int i = 0; i < K; ++i) x[i] = 1.0 + 0.7071067811865476 * (i + 1) + 0.013 * ((i + 1) * (i + 1) % 7);
+    c.h.assign((size_t)K * K, 0.0);
+    c.g.assign((size_t)K * K * K * K, 0.0);
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j) c.h[(size_t)i * K + j] = x[i] + x[j];
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < K; ++j)
+            for (int k = 0; k < K; ++k)
+                for (int l = 0; l < K; ++l)
+                    c.g[(((size_t)i * K + j) * K + k) * K + l] = (x[i] + x[j]) * (x[k] + x[l]);
+}
+}  // namespace
+
+dmrg_status dmrg_query_workspace(const dmrg_ctx* cctx, int32_t what, const void* args, int64_t* bytes) {
+    if (!args || !bytes) return fail(DMRG_E_ARG, "null argument");
+    *bytes = 0;
+    dmrg_ctx* ctx = const_cast<dmrg_ctx*>(cctx);
+    dmrg_ctx local;
+    if (!ctx) {
+        if (what != DMRG_WS_BLOCK && what != DMRG_WS_DAVIDSON)
+            return fail(DMRG_E_ARG, "this query needs the context of the operator sets");
+        local.arena.init(reinterpret_cast<void*>(uintptr_t(1) << 12), 0);
+        ctx = &local;
+        if (what == DMRG_WS_BLOCK) {
+            const dmrg_ws_block* a = (const dmrg_ws_block*)args;
+            if (a->K < 4 || a->K % 2 || a->K > 512) return fail(DMRG_E_ARG, "K must be even, 4 <= K <= 512");
+            if ((a->n_elec + a->two_sz) % 2 || a->n_elec < 0 || std::abs(a->two_sz) > a->n_elec)
+                return fail(DMRG_E_ARG, "inconsistent n_elec / two_sz");
+            if (a->n_proc < 1 || a->proc_id < 1 || a->proc_id > a->n_proc)
+                return fail(DMRG_E_ARG, "bad n_proc / proc_id");
+            local.K = a->K;
+            local.na = (a->n_elec + a->two_sz) / 2;
+            local.nb = (a->n_elec - a->two_sz) / 2;
+            local.n_proc = a->n_proc;
+            local.proc_id = a->proc_id;
+            generic_integrals(local);
+            apply_share_mask(&local);
+            local.has_ints = true;
+        }
+    }
+    DryScope dry(ctx);
+    dmrg_status st = DMRG_OK;
+    switch (what) {
+        case DMRG_WS_BLOCK: {
+            const dmrg_ws_block* a = (const dmrg_ws_block*)args;
+            dmrg_opset* o = nullptr;
+            st = dmrg_build_block(ctx, a->side, a->n_sites, a->isometries, a->scheme, &o, nullptr);
+            dmrg_opset_free(o);
+            break;
+        }
+        case DMRG_WS_TRANSFORM: {
+            const dmrg_ws_transform* a = (const dmrg_ws_transform*)args;
+            if (!a->right) return fail(DMRG_E_ARG, "null argument");
+            dmrg_opset copy;
+            static_cast<OpSetImpl&>(copy) = static_cast<const OpSetImpl&>(*a->right);
+            copy.ctx = ctx;
+            st = dmrg_normal_to_complementary(ctx, &copy, nullptr);
+            free_set(ctx, copy);
+            break;
+        }
+        case DMRG_WS_HEFF: {
+            const dmrg_ws_heff* a = (const dmrg_ws_heff*)args;
+            dmrg_heff* H = nullptr;
+            st = dmrg_heff_create(ctx, a->left, a->right, nullptr, a->n_roots, a->precision, &H, nullptr);
+            dmrg_heff_free(H);
+            break;
+        }
+        case DMRG_WS_DAVIDSON: {
+            const dmrg_ws_davidson* a = (const dmrg_ws_davidson*)args;
+            if (a->dim < 1 || a->n_roots < 1 || a->n_roots > 16) return fail(DMRG_E_ARG, "bad dim / n_roots");
+            if (ctx->arena.alloc(dav_workspace_bytes(a->dim, a->n_roots, &a->opts)) < 0)
+                st = fail(DMRG_E_WORKSPACE, "dry run");
+            break;
+        }
+        case DMRG_WS_RENORMALIZE: {
+            const dmrg_ws_renorm* a = (const dmrg_ws_renorm*)args;
+            dmrg_opset* o = nullptr;
+            st = dmrg_renormalize(ctx, a->in, a->isometry, &o, nullptr);
+            dmrg_opset_free(o);
+            break;
+        }
+        default:
+            return fail(DMRG_E_ARG, "unknown workspace query");
+    }
+    if (st != DMRG_OK) return st;
+    *bytes = ctx->arena.high;
     return DMRG_OK;
 }
 

@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <tuple>
@@ -20,6 +22,10 @@ extern "C" const char* dmrg_last_error(void) { return dmrg::g_last_error.c_str()
 namespace dmrg {
 
 const QN kSiteQ[4] = {QN(0, 0), QN(1, 0), QN(0, 1), QN(1, 1)};
+
+double wall_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 dmrg_status fail(dmrg_status s, const std::string& msg) {
     g_last_error = msg;
@@ -115,6 +121,7 @@ void Arena::init(void* p, int64_t n) {
     const int64_t start = (int64_t)((256 - ((uintptr_t)p & 255)) & 255);
     if (n > start) free_[start] = n - start;
     used = peak = 0;
+    high = start;
 }
 
 int64_t Arena::alloc(int64_t n) {
@@ -128,6 +135,7 @@ int64_t Arena::alloc(int64_t n) {
             live_[off] = n;
             used += n;
             peak = std::max(peak, used);
+            high = std::max(high, off + n);
             return off;
         }
     }
@@ -168,6 +176,8 @@ dmrg_status alloc_set(Ctx* ctx, OpSetImpl& s) {
     s.dev = (double*)(ctx->arena.base + off);
     return DMRG_OK;
 }
+
+int64_t set_bytes(const OpSetImpl& s) { return (std::max<int64_t>(s.elems, 1) * 8 + 255) / 256 * 256; }
 
 void free_set(Ctx* ctx, OpSetImpl& s) {
     if (s.region >= 0) ctx->arena.release(s.region);
@@ -329,9 +339,9 @@ M4 Ctx::site_Q(int n, int p, int q) const {
 }
 
 // ---------------------------------------------------------------------------
-dmrg_status make_iso(const Basis& old, const dmrg_bsm* bsm, Iso& out) {
+dmrg_status make_iso(const Basis& old, const dmrg_bsm* bsm, Iso& out, bool need_data) {
     if (!bsm || bsm->n_blocks <= 0 || !bsm->qn_col || !bsm->rows || !bsm->cols || !bsm->offset ||
-        !bsm->data)
+        (need_data && !bsm->data))
         return fail(DMRG_E_ARG, "isometry descriptor incomplete");
     if (bsm->dtype != DMRG_F64) return fail(DMRG_E_ARG, "isometries must be float64");
     std::vector<std::pair<QN, int>> order;
@@ -415,11 +425,12 @@ void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int 
     }
 }
 
-// Tiles taller than kMaxRows are split exactly: output rows into row tiles,
+// Tiles taller than kTallRows are split exactly: output rows into row tiles,
 // the inner dimension mu of X . U into chunks (a group becomes one group per
-// chunk; its identity part follows the output rows).
+// chunk; its identity part follows the output rows).  Tiles up to kTallRows
+// run whole on the tall kernel.
 void split_large(WorkList& w) {
-    const int CAP = dmrgk::kMaxRows;
+    const int CAP = dmrgk::kTallRows;
     bool need = false;
     for (auto& T : w.task)
         for (const dmrgk::Task& t : T) {
@@ -615,11 +626,27 @@ void balance_work(WorkList& w, int target_tasks) {
 }
 
 // Every element a task can touch must lie inside its buffer: checked on the
-// host before any work list reaches the device.
+// host before any work list reaches the device.  The kernels address an
+// operand through a 64-bit block origin plus a 32-bit byte offset (scalar base
+// + vector offset loads), with the in-block element index formed in 32-bit
+// signed arithmetic; so the span of every operand, from its origin to the last
+// element a task reads or writes, must stay below 2^32 bytes at 8-byte
+// elements (the lists are shared by the FP64 and FP32 products).  A longer
+// operand is reported as DMRG_E_UNSUPPORTED rather than wrapping silently.
 dmrg_status validate_work(WorkList& w, const int64_t* size) {
     split_large(w);
+    bool span_ok = true;
     auto in = [&](int buf, int64_t first, int64_t last) {
+        if (last - first >= kMaxOperandSpan) {
+            span_ok = false;
+            return false;
+        }
         return buf >= 0 && buf < dmrgk::kMaxBuf && first >= 0 && last < size[buf] && first <= last;
+    };
+    auto bad = [&](const char* what) {
+        return span_ok ? fail(DMRG_E_STATE, std::string("work list: ") + what)
+                       : fail(DMRG_E_UNSUPPORTED, std::string("work list: ") + what +
+                                                      " (operand spans 2^32 bytes or more)");
     };
     for (int cls = 0; cls < dmrgk::kNumClass; ++cls) {
         const int cap = dmrgk::class_rows(cls);
@@ -631,7 +658,7 @@ dmrg_status validate_work(WorkList& w, const int64_t* size) {
                 return fail(DMRG_E_STATE, "work list: bad task shape");
             if (local ? !in(t.cbuf & 15, t.c_off, t.c_off + (int64_t)t.m * t.ncol - 1)
                       : !in(t.cbuf & 15, t.c_off, t.c_off + (int64_t)(t.m - 1) * t.ldc + t.n - 1))
-                return fail(DMRG_E_STATE, "work list: output out of bounds");
+                return bad("output out of bounds");
             if (t.g0 == lg0 && t.g1 == lg1) continue;
             lg0 = t.g0;
             lg1 = t.g1;
@@ -647,7 +674,7 @@ dmrg_status validate_work(WorkList& w, const int64_t* size) {
                     const int64_t last = tr ? G.x_off + (int64_t)(G.mu - 1) * G.ldx + t.m - 1
                                             : G.x_off + (int64_t)(t.m - 1) * G.ldx + G.mu - 1;
                     if ((tr ? G.ldx < t.m : G.ldx < G.mu) || !in(G.flags & 7, G.x_off, last))
-                        return fail(DMRG_E_STATE, "work list: X operand out of bounds");
+                        return bad("X operand out of bounds");
                 }
                 if (G.c0 < 0 || G.c1 > (int)w.contribs.size() || G.c0 > G.c1)
                     return fail(DMRG_E_STATE, "work list: bad contribution range");
@@ -663,13 +690,13 @@ dmrg_status validate_work(WorkList& w, const int64_t* size) {
                     if (ida) {          // U += alpha B[0:mu, 0:n]
                         const int64_t last = tb ? q.b_off + (int64_t)(t.n - 1) * q.ldb + G.mu - 1
                                                 : q.b_off + (int64_t)(G.mu - 1) * q.ldb + t.n - 1;
-                        if (!in(bbuf, q.b_off, last)) return fail(DMRG_E_STATE, "work list: B (A=I) out of bounds");
+                        if (!in(bbuf, q.b_off, last)) return bad("B (A=I) out of bounds");
                         continue;
                     }
                     if (idb) {          // U += alpha A[0:mu, 0:n]
                         const int64_t last = ta ? q.a_off + (int64_t)(t.n - 1) * q.lda + G.mu - 1
                                                 : q.a_off + (int64_t)(G.mu - 1) * q.lda + t.n - 1;
-                        if (!in(abuf, q.a_off, last)) return fail(DMRG_E_STATE, "work list: A (B=I) out of bounds");
+                        if (!in(abuf, q.a_off, last)) return bad("A (B=I) out of bounds");
                         continue;
                     }
                     if (q.k < 1) return fail(DMRG_E_STATE, "work list: empty contraction");
@@ -677,14 +704,14 @@ dmrg_status validate_work(WorkList& w, const int64_t* size) {
                                           : q.a_off + (int64_t)(G.mu - 1) * q.lda + q.k - 1;
                     const int64_t lb = tb ? q.b_off + (int64_t)(t.n - 1) * q.ldb + q.k - 1
                                           : q.b_off + (int64_t)(q.k - 1) * q.ldb + t.n - 1;
-                    if (!in(abuf, q.a_off, la)) return fail(DMRG_E_STATE, "work list: A out of bounds");
-                    if (!in(bbuf, q.b_off, lb)) return fail(DMRG_E_STATE, "work list: B out of bounds");
+                    if (!in(abuf, q.a_off, la)) return bad("A out of bounds");
+                    if (!in(bbuf, q.b_off, lb)) return bad("B out of bounds");
                 }
             }
         }
     }
     for (const dmrgk::Reduce& r : w.reduces) {
-        if (r.m < 1 || r.m > dmrgk::kMaxRows || r.ncol < 1 || r.ncol > dmrgk::kMaxCols || r.col0 < 0 ||
+        if (r.m < 1 || r.m > dmrgk::kTallRows || r.ncol < 1 || r.ncol > dmrgk::kMaxCols || r.col0 < 0 ||
             r.col0 + r.ncol > r.ldc || r.nslot < 1)
             return fail(DMRG_E_STATE, "work list: bad reduction shape");
         if (!in(r.cbuf & 15, r.c_off, r.c_off + (int64_t)(r.m - 1) * r.ldc + r.col0 + r.ncol - 1))
@@ -693,6 +720,15 @@ dmrg_status validate_work(WorkList& w, const int64_t* size) {
             return fail(DMRG_E_STATE, "work list: partial tiles out of bounds");
     }
     return DMRG_OK;
+}
+
+int64_t work_bytes(const WorkList& w) {
+    int64_t bytes = 0;
+    for (int c = 0; c < dmrgk::kNumClass; ++c) bytes += ((int64_t)w.task[c].size() * sizeof(dmrgk::Task) + 255) & ~int64_t(255);
+    bytes += ((int64_t)w.groups.size() * sizeof(dmrgk::Group) + 255) & ~int64_t(255);
+    bytes += ((int64_t)w.contribs.size() * sizeof(dmrgk::Contrib) + 255) & ~int64_t(255);
+    bytes += ((int64_t)w.reduces.size() * sizeof(dmrgk::Reduce) + 255) & ~int64_t(255);
+    return std::max<int64_t>(bytes, 256);
 }
 
 dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
@@ -713,21 +749,22 @@ dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
     d.region = reg;
     char* base = ctx->arena.base + reg;
     hipStream_t s = (hipStream_t)stream;
+    const bool dev = !ctx->dry;
     for (int c = 0; c < dmrgk::kNumClass; ++c) {
         d.task[c] = (dmrgk::Task*)(base + toff[c]);
         d.ntask[c] = (int)w.task[c].size();
         d.useful[c] = 0;
         for (const dmrgk::Task& t : w.task[c]) d.useful[c] += task_useful_flops(w, t);
-        if (!w.task[c].empty())
+        if (dev && !w.task[c].empty())
             DMRG_HIP(hipMemcpyAsync(d.task[c], w.task[c].data(), w.task[c].size() * sizeof(dmrgk::Task),
                                     hipMemcpyHostToDevice, s));
     }
     d.groups = (dmrgk::Group*)(base + goff);
     d.contribs = (dmrgk::Contrib*)(base + coff);
-    if (!w.groups.empty())
+    if (dev && !w.groups.empty())
         DMRG_HIP(hipMemcpyAsync(d.groups, w.groups.data(), w.groups.size() * sizeof(dmrgk::Group),
                                 hipMemcpyHostToDevice, s));
-    if (!w.contribs.empty())
+    if (dev && !w.contribs.empty())
         DMRG_HIP(hipMemcpyAsync(d.contribs, w.contribs.data(), w.contribs.size() * sizeof(dmrgk::Contrib),
                                 hipMemcpyHostToDevice, s));
     d.lds_records = true;
@@ -735,10 +772,10 @@ dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
         for (const dmrgk::Task& t : T) d.lds_records = d.lds_records && records_fit(w, t);
     d.reduces = (dmrgk::Reduce*)(base + roff);
     d.nred = (int)w.reduces.size();
-    if (!w.reduces.empty())
+    if (dev && !w.reduces.empty())
         DMRG_HIP(hipMemcpyAsync(d.reduces, w.reduces.data(), w.reduces.size() * sizeof(dmrgk::Reduce),
                                 hipMemcpyHostToDevice, s));
-    DMRG_HIP(hipStreamSynchronize(s));   // host vectors may be released after return
+    if (dev) DMRG_HIP(hipStreamSynchronize(s));   // host vectors may be released after return
     return DMRG_OK;
 }
 
@@ -827,6 +864,40 @@ void plan_wsums(const OpSetImpl& src, WSumPlan& plan, OpSetImpl& temps) {
     }
 }
 
+// The source family is the B operand [nin x stride]; its span from a
+// contribution's origin must stay below kMaxOperandSpan, so the sum over the
+// operator index is cut into chunks of at most kc operators (one contribution
+// each, summed in order into the same tile).  Output rows go in groups of at
+// most 64 (fewer for very large operators) for the same reason.
+// DMRG_FAMILY_CHUNK_OPS lowers kc (a GPU test forces the chunked path).
+void family_chunks(int64_t stride, int64_t& kc, int& rchunk) {
+    kc = kMaxOperandSpan / std::max<int64_t>(stride, 1);
+    if (const char* e = std::getenv("DMRG_FAMILY_CHUNK_OPS")) kc = std::min<int64_t>(kc, std::max(1, std::atoi(e)));
+    rchunk = (int)std::min<int64_t>(64, kMaxOperandSpan / std::max<int64_t>(stride, 1));
+}
+
+int64_t wsum_work_bytes(const OpSetImpl& src, const WSumPlan& plan) {
+    std::map<int, int> rows;   // input family -> requests
+    for (const WSumReq& r : plan.reqs) rows[r.fam]++;
+    int64_t worst = 0;
+    for (auto& kv : rows) {
+        const Family& F = src.fams[kv.first];
+        const int64_t nin = (int64_t)F.keys.size();
+        int64_t kc;
+        int rchunk;
+        family_chunks(F.stride, kc, rchunk);
+        if (kc < 1 || rchunk < 1) continue;
+        const int64_t ngroup = (kv.second + rchunk - 1) / rchunk;
+        const int64_t ncontrib = ngroup * ((nin + kc - 1) / kc);
+        const int64_t ntask = ngroup * ((F.stride + dmrgk::kMaxCols - 1) / dmrgk::kMaxCols);
+        const int64_t b = ((nin * kv.second * 8 + 255) / 256 * 256) + ntask * (int64_t)sizeof(dmrgk::Task) +
+                          ngroup * (int64_t)sizeof(dmrgk::Group) + ncontrib * (int64_t)sizeof(dmrgk::Contrib) +
+                          (dmrgk::kNumClass + 3) * 256;
+        worst = std::max(worst, b);
+    }
+    return worst;
+}
+
 dmrg_status family_gemm(Ctx* ctx, const std::vector<double>& W, const OpSetImpl& src, int sf,
                         const OpSetImpl& dst, int df, int row0, int nrows, void* stream) {
     const Family& F = src.fams[sf];
@@ -838,33 +909,41 @@ dmrg_status family_gemm(Ctx* ctx, const std::vector<double>& W, const OpSetImpl&
     if (stride > INT32_MAX) return fail(DMRG_E_UNSUPPORTED, "operator larger than 2^31 elements");
     if ((int64_t)W.size() != (int64_t)nrows * nin) return fail(DMRG_E_ARG, "family_gemm: weight shape");
     if (nin == 0) {
-        DMRG_HIP(hipMemsetAsync(dst.dev + D.base + (int64_t)row0 * stride, 0, (size_t)nrows * stride * 8,
-                                (hipStream_t)stream));
+        if (!ctx->dry)
+            DMRG_HIP(hipMemsetAsync(dst.dev + D.base + (int64_t)row0 * stride, 0, (size_t)nrows * stride * 8,
+                                    (hipStream_t)stream));
         return DMRG_OK;
     }
+    const double t0 = wall_s();
     const int64_t wreg = ctx->arena.alloc((int64_t)W.size() * 8);
     if (wreg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for integral weights");
     double* wdev = (double*)(ctx->arena.base + wreg);
     hipStream_t s = (hipStream_t)stream;
-    int e = (int)hipMemcpyAsync(wdev, W.data(), W.size() * 8, hipMemcpyHostToDevice, s);
+    int e = ctx->dry ? 0 : (int)hipMemcpyAsync(wdev, W.data(), W.size() * 8, hipMemcpyHostToDevice, s);
     if (e) { ctx->arena.release(wreg); return hip_fail(e, "weights upload"); }
+    int64_t kc;
+    int rchunk;
+    family_chunks(stride, kc, rchunk);
+    if (kc < 1) return fail(DMRG_E_UNSUPPORTED, "operator of 2^32 bytes or more");
     WorkList wl;
-    for (int r0 = 0; r0 < nrows; r0 += 64) {
-        const int rows = std::min(64, nrows - r0);
+    for (int r0 = 0; r0 < nrows; r0 += rchunk) {
+        const int rows = std::min(rchunk, nrows - r0);
         const int g0 = (int)wl.groups.size();
         dmrgk::Group g{};
         g.xid_coef = 1.0;
         g.mu = rows;
         g.c0 = (int)wl.contribs.size();
-        dmrgk::Contrib c{};
-        c.a_off = (int64_t)r0 * nin;
-        c.lda = nin;
-        c.b_off = F.base;
-        c.ldb = (int)stride;
-        c.k = nin;
-        c.alpha = 1.0;
-        c.flags = 0 | (1 << 3);
-        wl.contribs.push_back(c);
+        for (int64_t k0 = 0; k0 < nin; k0 += kc) {
+            dmrgk::Contrib c{};
+            c.a_off = (int64_t)r0 * nin + k0;
+            c.lda = nin;
+            c.b_off = F.base + k0 * stride;
+            c.ldb = (int)stride;
+            c.k = (int)std::min<int64_t>(kc, nin - k0);
+            c.alpha = 1.0;
+            c.flags = 0 | (1 << 3);
+            wl.contribs.push_back(c);
+        }
         g.c1 = (int)wl.contribs.size();
         wl.groups.push_back(g);
         emit_block_tasks(wl, 3, D.base + (int64_t)(row0 + r0) * stride, (int)stride, rows, (int)stride,
@@ -878,15 +957,20 @@ dmrg_status family_gemm(Ctx* ctx, const std::vector<double>& W, const OpSetImpl&
     dmrg_status st = validate_work(wl, sz);
     if (st == DMRG_OK) st = upload_work(ctx, wl, dw, stream);
     if (st != DMRG_OK) { ctx->arena.release(wreg); return st; }
+    const double t1 = wall_s();
+    ctx->tm[TM_WSUM_HOST] += t1 - t0;
     dmrgk::Bases<double> b{};
     b.p[0] = wdev;
     b.p[1] = src.dev;
     b.p[3] = dst.dev;
-    st = run_work_f64(dw, b, 1, stream);
-    if (st == DMRG_OK) {
-        e = (int)hipStreamSynchronize(s);
-        if (e) st = hip_fail(e, "family gemm");
+    if (!ctx->dry) {
+        st = run_work_f64(dw, b, 1, stream);
+        if (st == DMRG_OK) {
+            e = (int)hipStreamSynchronize(s);
+            if (e) st = hip_fail(e, "family gemm");
+        }
     }
+    ctx->tm[TM_WSUM_DEV] += wall_s() - t1;
     free_work(ctx, dw);
     ctx->arena.release(wreg);
     return st;

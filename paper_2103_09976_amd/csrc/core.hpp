@@ -115,6 +115,7 @@ struct Arena {
     std::map<int64_t, int64_t> free_;   // offset -> size
     std::map<int64_t, int64_t> live_;
     int64_t used = 0, peak = 0;
+    int64_t high = 0;                   // highest end offset ever allocated
     void init(void* p, int64_t n);
     int64_t alloc(int64_t n);           // -1 on failure
     void release(int64_t off);
@@ -158,9 +159,19 @@ struct M4 {
     bool zero() const;
 };
 
+// host wall clock (seconds), for the per-phase timing printed under DMRG_VERBOSE
+double wall_s();
+// indices of Ctx::tm, accumulated over a block build
+enum { TM_GROW = 0, TM_PLAN, TM_WSUM_HOST, TM_WSUM_DEV, TM_REN_HOST, TM_REN_DEV, TM_N };
+
 struct Ctx {
     int device = 0;
     Arena arena;
+    double tm[TM_N] = {0};
+    // Dry run (workspace queries): every arena allocation and release happens
+    // as in a real call, but no device work is issued and no device memory is
+    // touched; the arena's high-water mark then gives the size the call needs.
+    bool dry = false;
     bool has_ints = false;
     int K = 0, na = 0, nb = 0;
     double e_core = 0.0;
@@ -202,11 +213,16 @@ struct Iso {
     std::vector<int> d;                // rows
     std::vector<std::array<int, 4>> seg;   // row offset of segment s (-1 absent)
 };
-dmrg_status make_iso(const Basis& old, const dmrg_bsm* bsm, Iso& out);
+// need_data = false (dry runs): the isometry's device data may be NULL
+dmrg_status make_iso(const Basis& old, const dmrg_bsm* bsm, Iso& out, bool need_data = true);
+// arena bytes of a Davidson workspace (davidson.cpp)
+int64_t dav_workspace_bytes(int64_t dim, int k, const dmrg_dav_opts* opts);
 
 // allocate + lay out an opset region
 dmrg_status alloc_set(Ctx* ctx, OpSetImpl& s);
 void free_set(Ctx* ctx, OpSetImpl& s);
+// arena bytes of a laid-out set (as alloc_set takes them)
+int64_t set_bytes(const OpSetImpl& s);
 
 // ------------- work lists ---------------------------------------------------
 struct WorkList {
@@ -232,9 +248,17 @@ struct DevWork {
     double useful[dmrgk::kNumClass] = {};   // useful MFMA flops per class (one vector)
 };
 dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
+// arena bytes upload_work takes for a list
+int64_t work_bytes(const WorkList& w);
 // splits tiles above kMaxRows rows, then checks every operand of every task on the
 // host; size[b] = elements of buffer b
 dmrg_status validate_work(WorkList& w, const int64_t* size);
+// Largest span (elements, origin to last element) of one operand of a task:
+// 2^32 bytes of 8-byte elements (the kernels' in-block byte offsets are 32-bit).
+constexpr int64_t kMaxOperandSpan = (int64_t(1) << 32) / 8;
+// Integral-weighted temporaries of one growth batch (bytes): operators are
+// grown and transformed in batches whose temporaries stay below this.
+constexpr int64_t kGrowBatchBytes = int64_t(8) << 30;
 void split_large(WorkList& w);
 // Splits the group ranges of expensive tasks into chunks of about
 // 1/target_tasks of the total cost each (chunks write partial tiles that a
@@ -277,6 +301,10 @@ dmrg_status family_gemm(Ctx* ctx, const std::vector<double>& W, const OpSetImpl&
 // runs the GEMMs once `temps` is allocated; synchronises the stream
 dmrg_status exec_wsums(Ctx* ctx, const OpSetImpl& src, const WSumPlan& plan, const OpSetImpl& temps,
                        void* stream);
+// largest transient arena bytes (weights + work list) of one family GEMM of exec_wsums
+int64_t wsum_work_bytes(const OpSetImpl& src, const WSumPlan& plan);
+// rows of one family GEMM group, operators per contribution (span bound)
+void family_chunks(int64_t stride, int64_t& kc, int& rchunk);
 
 // operators of a block grown by one site, in transition form
 struct Grown {

@@ -88,6 +88,8 @@ struct dmrg_heff {
     int64_t op_bytes64 = 0;
     int n2 = 0, n1 = 0, nh = 0;
     size_t ntask = 0, ngroup = 0, ncontrib = 0;
+    int precision = DMRG_PREC_F32;      // DMRG_PREC_F64: FP64 products only
+    const dmrg_psi_layout* layout = nullptr;   // caller's layout during creation (NULL: default)
 };
 
 namespace dmrg {
@@ -199,22 +201,26 @@ static dmrg_status materialize(Ctx* C, std::vector<TransOp*> ops, const OpSetImp
     }
     int64_t sz[dmrgk::kMaxBuf] = {0};
     sz[0] = base.elems;
-    sz[1] = temps.dev ? temps.elems : base.elems;
+    sz[1] = temps.elems > 0 ? temps.elems : base.elems;
     sz[3] = out.elems;
     DevWork dw;
     st = validate_work(wl, sz);
     if (st == DMRG_OK) st = upload_work(C, wl, dw, stream);
     if (st != DMRG_OK) return st;
+    {
     dmrgk::Bases<double> bs{};
     bs.p[0] = base.dev;
     bs.p[1] = temps.dev ? temps.dev : base.dev;
     bs.p[3] = out.dev;
-    st = run_work_f64(dw, bs, 1, stream);
-    if (st == DMRG_OK) {
-        const int e = (int)hipStreamSynchronize((hipStream_t)stream);
-        if (e) st = hip_fail(e, "materialize");
+    if (!C->dry) {
+        st = run_work_f64(dw, bs, 1, stream);
+        if (st == DMRG_OK) {
+            const int e = (int)hipStreamSynchronize((hipStream_t)stream);
+            if (e) st = hip_fail(e, "materialize");
+        }
     }
     free_work(C, dw);
+    }
     if (st != DMRG_OK) return st;
     // rewrite the transitions
     std::map<TransOp*, std::vector<const Job*>> per;
@@ -257,6 +263,36 @@ static int buf_of(const dmrg_heff* H, const OpSetImpl* s) {
 }
 
 }  // namespace dmrg
+
+// The caller's wavefunction layout: every sub-block (a, s1, s2) once, tiling
+// [0, dim) exactly; the offsets replace the default ones.
+static dmrg_status apply_layout(dmrg_heff* H, const Basis& lb) {
+    const dmrg_psi_layout* L = H->layout;
+    const size_t n = H->blocks.size();
+    if (L->n_blocks != (int32_t)n || !L->qn_left || !L->site1 || !L->site2 || !L->offset)
+        return fail(DMRG_E_ARG, "psi layout: expected " + std::to_string(n) + " sub-blocks");
+    std::vector<int64_t> off(n, -1);
+    for (int i = 0; i < L->n_blocks; ++i) {
+        const int a = lb.find(QN(L->qn_left[2 * i], L->qn_left[2 * i + 1]));
+        const int s1 = L->site1[i], s2 = L->site2[i];
+        if (a < 0 || s1 < 0 || s1 > 3 || s2 < 0 || s2 > 3) return fail(DMRG_E_ARG, "psi layout: unknown sub-block");
+        const int bi = H->blk_index[(a * 4 + s1) * 4 + s2];
+        if (bi < 0) return fail(DMRG_E_ARG, "psi layout: sub-block outside the target sector");
+        if (off[bi] >= 0) return fail(DMRG_E_ARG, "psi layout: sub-block listed twice");
+        off[bi] = L->offset[i];
+    }
+    std::vector<std::pair<int64_t, size_t>> order;
+    for (size_t b = 0; b < n; ++b) order.push_back({off[b], b});
+    std::sort(order.begin(), order.end());
+    int64_t end = 0;
+    for (auto& o : order) {
+        if (o.first != end) return fail(DMRG_E_ARG, "psi layout: sub-blocks must tile [0, dim) without gaps");
+        const PsiBlock& B = H->blocks[o.second];
+        end += (int64_t)B.ma * B.mb;
+    }
+    for (size_t b = 0; b < n; ++b) H->blocks[b].off = off[b];
+    return DMRG_OK;
+}
 
 static dmrg_status build_heff(dmrg_heff* H, void* stream) {
     Ctx* C = H->ctx;
@@ -364,6 +400,10 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
                 off += (int64_t)lb.m[a] * rb.m[b];
             }
     H->dim = off;
+    if (H->layout) {
+        dmrg_status ls = apply_layout(H, lb);
+        if (ls != DMRG_OK) return ls;
+    }
     // per term: components by bra site state
     struct TI { std::vector<const Comp*> x[4], y[4]; int piY; };
     std::vector<TI> ti(terms.size());
@@ -672,9 +712,11 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         H->dblocks = (dmrgk::DiagBlock*)base;
         H->dterms = (dmrgk::DiagTerm*)(base + ((int64_t)dbl.size() * sizeof(dmrgk::DiagBlock) + 255) / 256 * 256);
         H->n_dblocks = (int)dbl.size();
-        DMRG_HIP(hipMemcpy(H->dblocks, dbl.data(), dbl.size() * sizeof(dmrgk::DiagBlock), hipMemcpyHostToDevice));
-        if (!dtm.empty())
-            DMRG_HIP(hipMemcpy(H->dterms, dtm.data(), dtm.size() * sizeof(dmrgk::DiagTerm), hipMemcpyHostToDevice));
+        if (!C->dry) {
+            DMRG_HIP(hipMemcpy(H->dblocks, dbl.data(), dbl.size() * sizeof(dmrgk::DiagBlock), hipMemcpyHostToDevice));
+            if (!dtm.empty())
+                DMRG_HIP(hipMemcpy(H->dterms, dtm.data(), dtm.size() * sizeof(dmrgk::DiagTerm), hipMemcpyHostToDevice));
+        }
     }
     return DMRG_OK;
 }
@@ -710,7 +752,7 @@ static dmrg_status ensure_f32(dmrg_heff* H, void* stream) {
     for (int i = 0; i < 8; ++i) {
         if (!sets[i] || !sets[i]->dev) continue;
         H->f32[i] = (float*)(base + off[i]);
-        DMRG_HIP(dmrgk::launch_cast_d2f(sets[i]->dev, H->f32[i], sets[i]->elems, stream));
+        if (!H->ctx->dry) DMRG_HIP(dmrgk::launch_cast_d2f(sets[i]->dev, H->f32[i], sets[i]->elems, stream));
     }
     return DMRG_OK;
 }
@@ -719,10 +761,8 @@ Ctx* heff_ctx(const dmrg_heff* H) { return H->ctx; }
 
 extern "C" {
 
-dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right, int32_t n_roots,
-                             dmrg_heff** out, void* stream) {
-    if (!ctx || !left || !right || !out) return fail(DMRG_E_ARG, "null argument");
-    *out = nullptr;
+static dmrg_status check_heff_args(const dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right,
+                                   int32_t n_roots, int32_t precision) {
     if (!ctx->has_ints) return fail(DMRG_E_STATE, "integrals not set");
     const int K = ctx->K, KL = K / 2 - 1;
     if (left->side != DMRG_LEFT || left->kind != 0 || left->nsites != KL)
@@ -730,12 +770,31 @@ dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_o
     if (right->side != DMRG_RIGHT || right->kind != 1 || right->nsites != K - KL - 2)
         return fail(DMRG_E_ARG, "right must be a complementary right block of K/2-1 sites");
     if (n_roots < 1 || n_roots > 32) return fail(DMRG_E_ARG, "n_roots must be 1..32");
+    if (precision != DMRG_PREC_F64 && precision != DMRG_PREC_F32) return fail(DMRG_E_ARG, "bad precision");
+    return DMRG_OK;
+}
+
+dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right,
+                             const dmrg_psi_layout* layout, int32_t n_roots, int32_t precision, dmrg_heff** out,
+                             void* stream) {
+    if (!ctx || !left || !right || !out) return fail(DMRG_E_ARG, "null argument");
+    *out = nullptr;
+    dmrg_status st = check_heff_args(ctx, left, right, n_roots, precision);
+    if (st != DMRG_OK) return st;
     dmrg_heff* H = new dmrg_heff();
     H->ctx = ctx;
     H->Lb = left;
     H->Rb = right;
     H->n_roots = n_roots;
-    dmrg_status st = build_heff(H, stream);
+    H->precision = precision;
+    H->layout = layout;
+    st = build_heff(H, stream);
+    H->layout = nullptr;
+    if (st == DMRG_OK && precision == DMRG_PREC_F32) st = ensure_f32(H, stream);
+    if (st == DMRG_OK && !ctx->dry) {
+        const int e = (int)hipStreamSynchronize((hipStream_t)stream);
+        if (e) st = hip_fail(e, "heff create");
+    }
     if (st != DMRG_OK) {
         dmrg_heff_free(H);
         return st;
@@ -745,6 +804,27 @@ dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_o
 }
 
 int64_t dmrg_heff_dim(const dmrg_heff* H) { return H ? H->dim : -1; }
+
+int32_t dmrg_heff_psi_layout(const dmrg_heff* H, int32_t n, int32_t* qn_left, int32_t* site1, int32_t* site2,
+                             int32_t* qn_right, int64_t* rows, int64_t* cols, int64_t* offset) {
+    if (!H) return fail(DMRG_E_ARG, "null argument");
+    const Basis& lb = H->Lb->basis;
+    const Basis& rb = H->Rb->basis;
+    const int nb = (int)H->blocks.size();
+    for (int i = 0; i < nb && i < n; ++i) {
+        const PsiBlock& B = H->blocks[i];
+        if (qn_left) { qn_left[2 * i] = lb.q[B.a].a; qn_left[2 * i + 1] = lb.q[B.a].b; }
+        if (qn_right) { qn_right[2 * i] = rb.q[B.b].a; qn_right[2 * i + 1] = rb.q[B.b].b; }
+        if (site1) site1[i] = B.s1;
+        if (site2) site2[i] = B.s2;
+        if (rows) rows[i] = B.ma;
+        if (cols) cols[i] = B.mb;
+        if (offset) offset[i] = B.off;
+    }
+    return nb;
+}
+
+
 int64_t dmrg_heff_flops(const dmrg_heff* H) { return H ? H->flops : -1; }
 int64_t dmrg_heff_bytes(const dmrg_heff* H, int32_t precision) {
     if (!H) return -1;
@@ -777,8 +857,7 @@ dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec, cons
             b.vstride[2] = b.vstride[3] = H->dim;
             st = run_work_f64(H->work, b, nv, stream);
         } else {
-            st = ensure_f32(H, stream);
-            if (st != DMRG_OK) return st;
+            if (H->f32_region < 0) return fail(DMRG_E_STATE, "H_eff was created for FP64 products only");
             dmrgk::Bases<float> b{};
             for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
             b.p[dmrgk::kPartialBuf] = H->part ? (float*)H->part : H->f32[0];
@@ -807,8 +886,7 @@ int32_t dmrg_heff_profile(dmrg_heff* H, int32_t precision, const void* psi, void
         b.vstride[2] = b.vstride[3] = H->dim;
         st = run_work_timed_f64(H->work, b, t, stream);
     } else if (precision == DMRG_PREC_F32) {
-        st = ensure_f32(H, stream);
-        if (st != DMRG_OK) return st;
+        if (H->f32_region < 0) return fail(DMRG_E_STATE, "H_eff was created for FP64 products only");
         dmrgk::Bases<float> b{};
         for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
         b.p[dmrgk::kPartialBuf] = H->part ? (float*)H->part : H->f32[0];
@@ -835,7 +913,7 @@ dmrg_status dmrg_heff_diag(dmrg_heff* H, double* diag, void* stream) {
     return DMRG_OK;
 }
 
-dmrg_status dmrg_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_opset** out, void* stream) {
+dmrg_status dmrg_heff_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_opset** out, void* stream) {
     if (!H || !isometry || !out) return fail(DMRG_E_ARG, "null argument");
     *out = nullptr;
     dmrg_opset* o = new dmrg_opset();

@@ -373,6 +373,263 @@ __global__ __launch_bounds__(256, (SliceOcc<T, RT>::waves)) void slice_kernel(Ba
 }
 
 // ---------------------------------------------------------------------------
+// tall_kernel: output tiles with more than kMaxRows rows (or U rows), up to
+// kTallRows, one workgroup of four waves per 16-column slice.  Row tile j of
+// U and of the output belongs to wave j % 4 (five per wave at most).  Per
+// group, each wave forms its row tiles of U = sum_c alpha_c A_c B_c in MFMA
+// registers (A_c rows are its own, B_c is read by all four waves through the
+// CU's cache), adds the identity term to its own output rows, and writes
+// x_coef * U^T to LDS; after one barrier every wave runs X . U for its output
+// rows over all of U's rows, with U's fragments read from LDS.  U is thus
+// formed once per slice however tall the block, where the one-wave kernels
+// would recompute it for every 96-row tile.
+//
+// LDS holds U^T (16 columns x kTallRows rows, row stride LD): a lane's four
+// consecutive k of one column are one 16-byte (FP32) or two 16-byte (FP64)
+// reads, and LD is chosen so the sixteen columns of one read land in
+// distinct banks.  FP32 double-buffers U (one barrier per group: the buffer a
+// wave writes was last read before the previous barrier); FP64 keeps one
+// buffer and a second barrier, which leaves LDS for three workgroups per CU.
+// ---------------------------------------------------------------------------
+template <typename T> struct TallCfg;
+template <> struct TallCfg<float> {
+    static constexpr int nbuf = 2, ld = kTallRows + 4, waves = 3;
+};
+template <> struct TallCfg<double> {
+    static constexpr int nbuf = 1, ld = kTallRows + 6, waves = 2;
+};
+
+template <typename T, int NCT, bool LR>
+__global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T> Bargs,
+                                                                         const Task* __restrict__ tasks,
+                                                                         int ntask,
+                                                                         const Group* __restrict__ groups,
+                                                                         const Contrib* __restrict__ contribs) {
+    using V4 = typename Mfma<T>::v4;
+    constexpr int RW = kTallRows / 64;   // row tiles per wave
+    constexpr int LD = TallCfg<T>::ld;
+    constexpr int NB = TallCfg<T>::nbuf;
+    __shared__ __attribute__((aligned(16))) T sU[NB][16 * LD];
+    __shared__ Group sG[LR ? kRecG : 1];
+    __shared__ Contrib sC[LR ? kRecC : 1];
+    (void)Bargs;
+    (void)ntask;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int w = blockIdx.x % NCT;          // column slice of the task
+    const Task tk = tasks[blockIdx.x / NCT];  // the grid is exactly ntask * NCT workgroups
+    const int vec = blockIdx.y;
+    const int lr0 = lane & 15;
+    const int lk0 = lane >> 4;
+    const int ncv = min(tk.ncol, tk.n - tk.col0);
+    const int nrm = (tk.m + 15) >> 4;
+    Recs<LR> R;
+    if constexpr (LR) {
+        const int cb = stage_records(groups, contribs, tk.g0, tk.g1, sG, sC, tid, 256);
+        __syncthreads();
+        R = Recs<true>{sG, sC, tk.g0, cb};
+    } else {
+        R = Recs<false>{groups, contribs};
+    }
+    auto opaque = [](int x) { asm volatile("" : "+v"(x)); return x; };
+
+    V4 acc[RW];
+#pragma unroll
+    for (int t = 0; t < RW; ++t) acc[t] = V4{0, 0, 0, 0};
+    int buf = 0;
+
+    for (int g = tk.g0; g < tk.g1; ++g) {
+        const Group gr = R.group(g);
+        const int mu = gr.mu;
+        const int nru = (mu + 15) >> 4;
+        V4 U[RW];
+#pragma unroll
+        for (int t = 0; t < RW; ++t) U[t] = V4{0, 0, 0, 0};
+        for (int c = gr.c0; c < gr.c1; ++c) {
+            const Contrib ct = R.contrib(c);
+            const T alpha = (T)ct.alpha;
+            if (is_identity(ct.flags)) {
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                const int gcol = tk.col0 + 16 * w + lr;
+                const bool colok = 16 * w + lr < ncv;
+                const bool ida = (ct.flags & F_ID_A) != 0, idb = (ct.flags & F_ID_B) != 0;
+                const T* P = ida ? base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off
+                                 : base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
+                const bool tp = ida ? (ct.flags & F_TRANS_B) != 0 : (ct.flags & F_TRANS_A) != 0;
+                const int ld = ida ? ct.ldb : ct.lda;
+#pragma unroll
+                for (int t = 0; t < RW; ++t) {
+                    const int j = wv + 4 * t;
+                    if (j >= nru) continue;
+                    T x[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * j + Mfma<T>::row(lk, v);
+                        const bool ok = row < mu && colok;
+                        if (ida && idb)
+                            x[v] = (row + (int)ct.a_off == gcol) ? T(1) : T(0);
+                        else
+                            x[v] = ld_at(P, ok ? (tp ? (uint32_t)(gcol * ld + row) : (uint32_t)(row * ld + gcol)) : 0u);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * j + Mfma<T>::row(lk, v);
+                        U[t][v] += (row < mu && colok) ? alpha * x[v] : T(0);
+                    }
+                }
+                continue;
+            }
+            const T* Ap = base_ptr<T>(ct.flags & 7, vec) + ct.a_off;
+            const T* Bp = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
+            const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
+            const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                T fa[RW][4], fb[4];
+                {
+                    const int lr = opaque(lr0), lk = opaque(lk0);
+                    const int gcol = tk.col0 + 16 * w + lr;
+                    const bool colok = 16 * w + lr < ncv;
+                    const int kb = k0 + 4 * lk;
+                    const bool vec4 = k0 + 16 <= K;
+#pragma unroll
+                    for (int t = 0; t < RW; ++t) {
+                        const int j = wv + 4 * t;
+                        if (j >= nru) continue;
+                        const int row = 16 * j + lr;
+                        const bool rok = row < mu;
+                        if (!ta && vec4) {
+                            ld4_at(Ap, rok ? (uint32_t)(row * lda + kb) : 0u, fa[t]);
+                        } else {
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) {
+                                const int k = kb + s;
+                                const bool ok = rok && k < K;
+                                fa[t][s] = ld_at(Ap, ok ? (ta ? (uint32_t)(k * lda + row) : (uint32_t)(row * lda + k)) : 0u);
+                            }
+                        }
+                    }
+                    if (tb && vec4) {
+                        ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + kb) : 0u, fb);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int k = kb + s;
+                            const bool ok = colok && k < K;
+                            fb[s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gcol * ldb + k) : (uint32_t)(k * ldb + gcol)) : 0u);
+                        }
+                    }
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) fb[s] = (colok && kb + s < K) ? alpha * fb[s] : T(0);
+                }
+#pragma unroll
+                for (int t = 0; t < RW; ++t) {
+                    if (wv + 4 * t >= nru) continue;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) U[t] = Mfma<T>::mma(fa[t][s], fb[s], U[t]);
+                }
+            }
+        }
+        {
+            const int lk = opaque(lk0);
+#pragma unroll
+            for (int t = 0; t < RW; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (16 * (wv + 4 * t) + Mfma<T>::row(lk, v) >= mu) U[t][v] = T(0);
+        }
+        if (gr.xid_coef != 0.0) {   // identity X: output rows are U's rows (m == mu), same owner wave
+            const T xi = (T)gr.xid_coef;
+#pragma unroll
+            for (int t = 0; t < RW; ++t) acc[t] += xi * U[t];
+        }
+        if (gr.flags & G_HAS_X) {
+            T* su = sU[buf];
+            const T xc = (T)gr.x_coef;
+            {
+                const int lr = opaque(lr0), lk = opaque(lk0);
+#pragma unroll
+                for (int t = 0; t < RW; ++t) {
+                    const int j = wv + 4 * t;
+                    if (j >= nru) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) su[lr * LD + 16 * j + Mfma<T>::row(lk, v)] = xc * U[t][v];
+                }
+            }
+            __syncthreads();
+            const T* Xp = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
+            const bool tx = (gr.flags & G_TRANS_X) != 0;
+            const int ldx = gr.ldx;
+            for (int q = 0; q < nru; ++q) {
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                // B fragment: U[16q + 4 lk + s][lr], s = 0..3 (four consecutive k of U^T's row lr)
+                T ub[4];
+                {
+                    const T* p = su + lr * LD + 16 * q + 4 * lk;
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 v = *reinterpret_cast<const float4*>(p);
+                        ub[0] = v.x; ub[1] = v.y; ub[2] = v.z; ub[3] = v.w;
+                    } else {
+                        const double2 a = *reinterpret_cast<const double2*>(p);
+                        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+                        ub[0] = a.x; ub[1] = a.y; ub[2] = b.x; ub[3] = b.y;
+                    }
+                }
+                const bool full = 16 * q + 16 <= mu;
+                T xf[RW][4];
+#pragma unroll
+                for (int t = 0; t < RW; ++t) {
+                    const int i = wv + 4 * t;
+                    if (i >= nrm) continue;
+                    const int row = 16 * i + lr;
+                    const bool rok = row < tk.m;
+                    if (!tx && full) {
+                        ld4_at(Xp, rok ? (uint32_t)(row * ldx + 16 * q + 4 * lk) : 0u, xf[t]);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int k = 16 * q + 4 * lk + s;
+                            const bool ok = rok && k < mu;
+                            xf[t][s] = ld_at(Xp, ok ? (tx ? (uint32_t)(k * ldx + row) : (uint32_t)(row * ldx + k)) : 0u);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < RW; ++t) {
+                    if (wv + 4 * t >= nrm) continue;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[t] = Mfma<T>::mma(xf[t][s], ub[s], acc[t]);
+                }
+            }
+            if constexpr (NB == 1) __syncthreads();   // the single buffer is rewritten by the next group
+            else buf ^= 1;
+        }
+    }
+
+    const int cbuf = tk.cbuf & 15;
+    const bool accum = (tk.cbuf >> 8) & 1;
+    const bool local = (tk.cbuf >> 9) & 1;
+    T* Cp = const_cast<T*>(base_ptr<T>(cbuf, vec)) + tk.c_off + (local ? 0 : tk.col0);
+    const int mycol = 16 * w + lr0;
+    if (mycol < ncv) {
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+            const int i = wv + 4 * t;
+            if (i >= nrm) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * i + Mfma<T>::row(lk0, v);
+                if (row < tk.m) {
+                    T* d = Cp + (uint32_t)(row * tk.ldc + mycol);
+                    *d = accum ? *d + acc[t][v] : acc[t][v];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // wave_kernel: tiles of at most 16*RT rows (and U rows) x 16*CT columns.  One
 // wave per task, four independent tasks per workgroup, no LDS and no
 // barrier: MFMA fragments come straight from global memory and the
@@ -570,6 +827,20 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
 template <typename T, bool LR>
 static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
                           int nvec, hipStream_t s) {
+    if (cls >= kTallClass0) {   // tall classes: one workgroup per column slice
+        const int nct = cls - kTallClass0 + 1;
+        const dim3 grid(ntask * nct, nvec), block(256);
+        switch (nct) {
+            case 1: hipLaunchKernelGGL((tall_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 2: hipLaunchKernelGGL((tall_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 3: hipLaunchKernelGGL((tall_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 4: hipLaunchKernelGGL((tall_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 5: hipLaunchKernelGGL((tall_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            case 6: hipLaunchKernelGGL((tall_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
+            default: return (int)hipErrorInvalidValue;
+        }
+        return (int)hipGetLastError();
+    }
     if (cls >= kNumTileClass) {   // wave classes: four tasks per workgroup
         const dim3 grid((ntask + 3) / 4, nvec), block(256);
         switch (cls - kNumTileClass) {
@@ -627,6 +898,8 @@ int launch_chain_f32(int cls, bool lds_records, const Task* t, int ntask, const 
 // slot are unconditional (indices past the tile are clamped to its last
 // element and their sums discarded), so they are all in flight together;
 // each element is still summed in slot order.
+// A tile of up to kMaxRows x kMaxCols elements takes one pass; taller tiles
+// (tall classes) take several passes over element ranges of that size.
 constexpr int kRedThreads = 512;
 constexpr int kRedPer = (kMaxRows * kMaxCols + kRedThreads - 1) / kRedThreads;
 
@@ -638,26 +911,28 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const Reduce* __res
     const bool accum = (r.cbuf >> 8) & 1;
     const T* P = b.p[kPartialBuf] + r.poff + (int64_t)vec * b.vstride[kPartialBuf];
     T* Cp = b.p[cbuf] + r.c_off + (int64_t)vec * b.vstride[cbuf];
-    const int slot = r.m * r.ncol;   // <= kMaxRows * kMaxCols (checked on the host)
+    const int slot = r.m * r.ncol;   // <= kTallRows * kMaxCols (checked on the host)
     const int tid = threadIdx.x;
-    T s[kRedPer];
+    for (int e0 = 0; e0 < slot; e0 += kRedPer * kRedThreads) {
+        T s[kRedPer];
 #pragma unroll
-    for (int i = 0; i < kRedPer; ++i) s[i] = 0;
-    for (int q = 0; q < r.nslot; ++q) {
-        const T* Pq = P + (int64_t)q * slot;
-        T v[kRedPer];
+        for (int i = 0; i < kRedPer; ++i) s[i] = 0;
+        for (int q = 0; q < r.nslot; ++q) {
+            const T* Pq = P + (int64_t)q * slot;
+            T v[kRedPer];
 #pragma unroll
-        for (int i = 0; i < kRedPer; ++i) v[i] = Pq[min(tid + i * kRedThreads, slot - 1)];
+            for (int i = 0; i < kRedPer; ++i) v[i] = Pq[min(e0 + tid + i * kRedThreads, slot - 1)];
 #pragma unroll
-        for (int i = 0; i < kRedPer; ++i) s[i] += v[i];
-    }
+            for (int i = 0; i < kRedPer; ++i) s[i] += v[i];
+        }
 #pragma unroll
-    for (int i = 0; i < kRedPer; ++i) {
-        const int e = tid + i * kRedThreads;
-        if (e >= slot) continue;
-        const int row = e / r.ncol, j = e - row * r.ncol;
-        T* d = Cp + (int64_t)row * r.ldc + r.col0 + j;
-        *d = accum ? *d + s[i] : s[i];
+        for (int i = 0; i < kRedPer; ++i) {
+            const int e = e0 + tid + i * kRedThreads;
+            if (e >= slot) continue;
+            const int row = e / r.ncol, j = e - row * r.ncol;
+            T* d = Cp + (int64_t)row * r.ldc + r.col0 + j;
+            *d = accum ? *d + s[i] : s[i];
+        }
     }
 }
 

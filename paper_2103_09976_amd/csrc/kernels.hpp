@@ -22,17 +22,21 @@
 
 namespace dmrgk {
 
-// Rows of an output tile and of U (inner dimension of X . U): at most six MFMA
-// row tiles; taller blocks are split exactly, and each split row tile
-// recomputes U.  Tiles whose rows all fit five row tiles (kShortRows) run a
-// kernel compiled for five: a wave's FP32 accumulators, U and one chunk's
-// fragments then fit 128 registers (four waves per SIMD) instead of 168
-// (three).
+// Rows of an output tile and of U (inner dimension of X . U) for the
+// one-wave-per-slice kernels: at most six MFMA row tiles.  Tiles whose rows
+// all fit five row tiles (kShortRows) run a kernel compiled for five: a wave's
+// FP32 accumulators, U and one chunk's fragments then fit 128 registers (four
+// waves per SIMD) instead of 168 (three).
 #ifndef DMRG_MAX_ROWS
 #define DMRG_MAX_ROWS 96
 #endif
 constexpr int kMaxRows = DMRG_MAX_ROWS;
 constexpr int kShortRows = 80;
+// Tiles with more than kMaxRows rows (or U rows), up to kTallRows, run the
+// tall kernel: one workgroup per 16-column slice, U formed once for all its
+// rows and shared through LDS, so no row tile recomputes it.  Blocks taller
+// than kTallRows are split exactly.
+constexpr int kTallRows = 320;
 constexpr int kMaxCols = 96;     // columns of an output tile
 constexpr int kMaxBuf = 9;       // buffer 8: partial tiles of split tasks
 
@@ -78,20 +82,25 @@ struct Bases {
 // (one wave each), with rows (and U rows) up to kShortRows (c < kColClasses)
 // or kMaxRows.  Wave classes kNumTileClass + (RT-1)*2 + (CT-1): tiles whose
 // rows and U rows fit 16*RT and whose columns fit 16*CT (RT, CT <= 2), one
-// wave each.
+// wave each.  Tall classes kTallClass0 + n: tiles of 16n+1 .. 16n+16 columns
+// with rows (or U rows) in (kMaxRows, kTallRows], one workgroup per slice.
 constexpr int kColClasses = kMaxCols / 16;
 constexpr int kNumTileClass = 2 * kColClasses;
-constexpr int kNumClass = kNumTileClass + 4;
+constexpr int kTallClass0 = kNumTileClass + 4;
+constexpr int kNumClass = kTallClass0 + kColClasses;
 inline int col_class(int ncol) { return (ncol + 15) / 16 - 1; }
 // rows: max of the tile rows and of every group's mu
 inline int task_class(int rows, int ncol) {
+    if (rows > kMaxRows) return kTallClass0 + col_class(ncol);
     if (rows <= 32 && ncol <= 32) return kNumTileClass + ((rows + 15) / 16 - 1) * 2 + (ncol + 15) / 16 - 1;
     return col_class(ncol) + (rows > kShortRows ? kColClasses : 0);
 }
 inline int class_rows(int cls) {
+    if (cls >= kTallClass0) return kTallRows;
     return cls < kNumTileClass ? (cls >= kColClasses ? kMaxRows : kShortRows) : 16 * ((cls - kNumTileClass) / 2 + 1);
 }
 inline int class_cols(int cls) {
+    if (cls >= kTallClass0) return 16 * (cls - kTallClass0 + 1);
     return cls < kNumTileClass ? 16 * (cls % kColClasses + 1) : 16 * ((cls - kNumTileClass) % 2 + 1);
 }
 

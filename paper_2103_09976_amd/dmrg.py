@@ -21,7 +21,7 @@ DMRG_LEFT, DMRG_RIGHT = 0, 1
 DMRG_SCHEME_NC, DMRG_SCHEME_CN = 0, 1
 DMRG_F64, DMRG_F32 = 0, 1
 DMRG_PREC_F64, DMRG_PREC_F32 = 0, 1
-DMRG_HEFF_LAUNCHES = 17   # kernel launches of one H_eff product (dmrg_heff_profile)
+DMRG_HEFF_LAUNCHES = 23   # kernel launches of one H_eff product (dmrg_heff_profile)
 
 SITE_Q = ((0, 0), (1, 0), (0, 1), (1, 1))
 
@@ -51,6 +51,36 @@ class DavStats(C.Structure):
                 ("ms_matvec", C.c_double)]
 
 
+class PsiLayout(C.Structure):
+    _fields_ = [("n_blocks", C.c_int32), ("qn_left", C.POINTER(C.c_int32)), ("site1", C.POINTER(C.c_int32)),
+                ("site2", C.POINTER(C.c_int32)), ("offset", C.POINTER(C.c_int64))]
+
+
+DMRG_WS_BLOCK, DMRG_WS_TRANSFORM, DMRG_WS_HEFF, DMRG_WS_DAVIDSON, DMRG_WS_RENORMALIZE = 0, 1, 2, 3, 4
+
+
+class WsBlock(C.Structure):
+    _fields_ = [("K", C.c_int32), ("n_elec", C.c_int32), ("two_sz", C.c_int32), ("n_proc", C.c_int32),
+                ("proc_id", C.c_int32), ("side", C.c_int32), ("n_sites", C.c_int32), ("scheme", C.c_int32),
+                ("isometries", C.POINTER(Bsm))]
+
+
+class WsTransform(C.Structure):
+    _fields_ = [("right", C.c_void_p)]
+
+
+class WsHeff(C.Structure):
+    _fields_ = [("left", C.c_void_p), ("right", C.c_void_p), ("n_roots", C.c_int32), ("precision", C.c_int32)]
+
+
+class WsDavidson(C.Structure):
+    _fields_ = [("dim", C.c_int64), ("n_roots", C.c_int32), ("opts", DavOpts)]
+
+
+class WsRenorm(C.Structure):
+    _fields_ = [("inp", C.c_void_p), ("isometry", C.POINTER(Bsm))]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -66,15 +96,26 @@ _SIGS = {
     "dmrg_build_block": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Bsm), C.c_int32,
                                      C.POINTER(C.c_void_p), C.c_void_p]),
     "dmrg_normal_to_complementary": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
-    "dmrg_heff_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
-                                     C.POINTER(C.c_void_p), C.c_void_p]),
+    "dmrg_heff_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PsiLayout), C.c_int32,
+                                     C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
     "dmrg_heff_dim": (C.c_int64, [C.c_void_p]),
+    "dmrg_heff_psi_layout": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dmrg_davidson_start": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(DavOpts),
+                                        C.POINTER(C.c_void_p), C.c_void_p]),
+    "dmrg_davidson_step": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double)]),
+    "dmrg_davidson_finish": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(DavStats)]),
+    "dmrg_davidson_free": (None, [C.c_void_p]),
+    "dmrg_heff_renormalize": (C.c_int32, [C.c_void_p, C.POINTER(Bsm), C.POINTER(C.c_void_p), C.c_void_p]),
+    "dmrg_query_workspace": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
     "dmrg_heff_apply": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
     "dmrg_heff_diag": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dmrg_davidson": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_double),
                                   C.POINTER(DavOpts), C.POINTER(DavStats), C.c_void_p]),
-    "dmrg_renormalize": (C.c_int32, [C.c_void_p, C.POINTER(Bsm), C.POINTER(C.c_void_p), C.c_void_p]),
+    "dmrg_renormalize": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(Bsm), C.POINTER(C.c_void_p),
+                                     C.c_void_p]),
     "dmrg_heff_flops": (C.c_int64, [C.c_void_p]),
     "dmrg_heff_bytes": (C.c_int64, [C.c_void_p, C.c_int32]),
     "dmrg_heff_terms": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -117,10 +158,11 @@ def _stream(torch):
 
 
 class Isometry:
-    """Device copy of one site isometry {q: U_q (d_q x m_q)} as a dmrg_bsm."""
+    """Device copy of one site isometry {q: U_q (d_q x m_q)} as a dmrg_bsm.
+    With device=None only the metadata is kept (data = NULL), which is what
+    the workspace queries read."""
 
     def __init__(self, iso: Dict[Tuple[int, int], np.ndarray], device):
-        import torch
         qs = sorted(iso)
         offs, rows, cols = [], [], []
         o = 0
@@ -130,8 +172,14 @@ class Isometry:
             rows.append(d)
             cols.append(m)
             o += d * m
-        host = np.concatenate([np.ascontiguousarray(iso[q], dtype=np.float64).ravel() for q in qs])
-        self.data = torch.from_numpy(host).to(device)
+        if device is None:
+            self.data = None
+            ptr = None
+        else:
+            import torch
+            host = np.concatenate([np.ascontiguousarray(iso[q], dtype=np.float64).ravel() for q in qs])
+            self.data = torch.from_numpy(host).to(device)
+            ptr = self.data.data_ptr()
         qn = np.array([x for q in qs for x in q], dtype=np.int32)
         self._qn = qn
         self._rows = np.array(rows, dtype=np.int64)
@@ -141,8 +189,7 @@ class Isometry:
                        self._qn.ctypes.data_as(C.POINTER(C.c_int32)),
                        self._rows.ctypes.data_as(C.POINTER(C.c_int64)),
                        self._cols.ctypes.data_as(C.POINTER(C.c_int64)),
-                       self._offs.ctypes.data_as(C.POINTER(C.c_int64)), DMRG_F64,
-                       C.c_void_p(self.data.data_ptr()))
+                       self._offs.ctypes.data_as(C.POINTER(C.c_int64)), DMRG_F64, C.c_void_p(ptr))
 
 
 class OpSet:
@@ -233,16 +280,89 @@ class Heff:
         stats = {f: getattr(st, f) for f, _ in DavStats._fields_}
         return np.array(list(e)), stats
 
+    def davidson_start(self, psi0, n_roots: int = 1, tol: float = 1e-6, max_iter: int = 300,
+                       max_subspace: int = 24, precision: int = DMRG_PREC_F64, switch_tol: float = 1e-4,
+                       fixed_iters: int = 0, precond_clamp: float = 0.0) -> "DavidsonSolve":
+        import torch
+        assert psi0.dtype == torch.float64 and psi0.numel() >= n_roots * self.dim
+        opts = DavOpts(max_iter, max_subspace, tol, precision, switch_tol, fixed_iters, precond_clamp)
+        out = C.c_void_p()
+        _check(load().dmrg_davidson_start(self.ptr, n_roots, C.c_void_p(psi0.data_ptr()), C.byref(opts),
+                                          C.byref(out), _stream(torch)))
+        return DavidsonSolve(out, n_roots)
+
+    def psi_layout(self):
+        """[(qn_left, s1, s2, qn_right, rows, cols, offset)] of the layout in use."""
+        lib = load()
+        n = lib.dmrg_heff_psi_layout(self.ptr, 0, None, None, None, None, None, None, None)
+        ql, qr = np.zeros(2 * n, np.int32), np.zeros(2 * n, np.int32)
+        s1, s2 = np.zeros(n, np.int32), np.zeros(n, np.int32)
+        rows, cols, off = np.zeros(n, np.int64), np.zeros(n, np.int64), np.zeros(n, np.int64)
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        lib.dmrg_heff_psi_layout(self.ptr, n, ptr(ql), ptr(s1), ptr(s2), ptr(qr), ptr(rows), ptr(cols), ptr(off))
+        return [((int(ql[2 * i]), int(ql[2 * i + 1])), int(s1[i]), int(s2[i]), (int(qr[2 * i]), int(qr[2 * i + 1])),
+                 int(rows[i]), int(cols[i]), int(off[i])) for i in range(n)]
+
     def renormalize(self, iso: Isometry) -> OpSet:
+        """The blocked L' operators transformed through the isometry adding d1."""
         import torch
         out = C.c_void_p()
-        _check(load().dmrg_renormalize(self.ptr, C.byref(iso.bsm), C.byref(out), _stream(torch)))
+        _check(load().dmrg_heff_renormalize(self.ptr, C.byref(iso.bsm), C.byref(out), _stream(torch)))
         return OpSet(self.ctx, out)
 
     def free(self):
         if self.ptr:
             load().dmrg_heff_free(self.ptr)
             self.ptr = None
+
+
+class DavidsonSolve:
+    """A block Davidson solve driven one iteration at a time."""
+
+    def __init__(self, ptr: C.c_void_p, n_roots: int):
+        self.ptr = ptr
+        self.n_roots = n_roots
+
+    def step(self):
+        """One iteration; returns (done, Ritz values, largest residual norm)."""
+        done = C.c_int32()
+        e = (C.c_double * self.n_roots)()
+        r = C.c_double()
+        _check(load().dmrg_davidson_step(self.ptr, C.byref(done), e, C.byref(r)))
+        return bool(done.value), np.array(list(e)), r.value
+
+    def finish(self, psi_out):
+        import torch
+        assert psi_out.dtype == torch.float64
+        e = (C.c_double * self.n_roots)()
+        st = DavStats()
+        _check(load().dmrg_davidson_finish(self.ptr, C.c_void_p(psi_out.data_ptr()), e, C.byref(st)))
+        return np.array(list(e)), {f: getattr(st, f) for f, _ in DavStats._fields_}
+
+    def free(self):
+        if self.ptr:
+            load().dmrg_davidson_free(self.ptr)
+            self.ptr = None
+
+
+def query_workspace(ctx, what: int, args) -> int:
+    """Arena bytes a call needs (dmrg_query_workspace); ctx may be None for the
+    block build and Davidson queries."""
+    b = C.c_int64()
+    _check(load().dmrg_query_workspace(ctx.ptr if ctx is not None else None, what, C.byref(args), C.byref(b)))
+    return int(b.value)
+
+
+def block_workspace(prob, side: int, scheme: int, ctx=None) -> int:
+    """Arena bytes of dmrg_build_block for one block of a synthetic problem,
+    from the isometries' metadata (no device memory needed)."""
+    isos = prob.left_iso if side == DMRG_LEFT else prob.right_iso
+    holders = [Isometry(u, None) for u in isos]
+    arr = (Bsm * len(holders))(*[h.bsm for h in holders])
+    n_elec = prob.target[0] + prob.target[1]
+    a = WsBlock(prob.K, n_elec, prob.target[0] - prob.target[1], prob.n_proc, prob.proc_id, side, len(holders),
+                scheme, arr)
+    return query_workspace(ctx, DMRG_WS_BLOCK, a)
 
 
 class Context:
@@ -276,11 +396,28 @@ class Context:
         import torch
         _check(load().dmrg_normal_to_complementary(self.ptr, right.ptr, _stream(torch)))
 
-    def heff_create(self, left: OpSet, right: OpSet, n_roots: int = 1) -> Heff:
+    def heff_create(self, left: OpSet, right: OpSet, n_roots: int = 1, precision: int = DMRG_PREC_F32,
+                    layout=None) -> Heff:
+        """layout: None (default order) or a list of (qn_left, s1, s2, offset)."""
         import torch
         out = C.c_void_p()
-        _check(load().dmrg_heff_create(self.ptr, left.ptr, right.ptr, n_roots, C.byref(out), _stream(torch)))
+        lay = None
+        if layout is not None:
+            n = len(layout)
+            self._lay = (np.array([x for l in layout for x in l[0]], np.int32), np.array([l[1] for l in layout], np.int32),
+                         np.array([l[2] for l in layout], np.int32), np.array([l[3] for l in layout], np.int64))
+            p = [a.ctypes.data_as(C.POINTER(t)) for a, t in zip(self._lay, (C.c_int32, C.c_int32, C.c_int32, C.c_int64))]
+            lay = C.byref(PsiLayout(n, *p))
+        _check(load().dmrg_heff_create(self.ptr, left.ptr, right.ptr, lay, n_roots, precision, C.byref(out),
+                                       _stream(torch)))
         return Heff(self, out)
+
+    def renormalize(self, block: OpSet, iso: Isometry) -> OpSet:
+        """`block` grown by its next site and transformed through `iso`."""
+        import torch
+        out = C.c_void_p()
+        _check(load().dmrg_renormalize(self.ptr, block.ptr, C.byref(iso.bsm), C.byref(out), _stream(torch)))
+        return OpSet(self, out)
 
     @property
     def arena_used(self) -> int:
@@ -297,7 +434,7 @@ class Context:
 
 
 def middle_step(prob, arena_bytes: int, scheme: Optional[str] = None, n_roots: int = 1,
-                device: int = 0):
+                device: int = 0, precision: int = DMRG_PREC_F32):
     """Set up one middle-site step of a synthetic problem on the GPU.
 
     Builds both blocks through the problem's isometries, applies the
@@ -316,5 +453,5 @@ def middle_step(prob, arena_bytes: int, scheme: Optional[str] = None, n_roots: i
     R = ctx.build_block(DMRG_RIGHT, ri, DMRG_SCHEME_CN if scheme == "CN" else DMRG_SCHEME_NC)
     if scheme == "CN":
         ctx.normal_to_complementary(R)
-    H = ctx.heff_create(L, R, n_roots)
+    H = ctx.heff_create(L, R, n_roots, precision)
     return ctx, L, R, H, (li, ri)

@@ -198,9 +198,9 @@ def test_mixed_vs_fp64_energy():
 
 @pytest.mark.parametrize("K,N,M,seed", [(12, 12, None, 81), (14, 14, 1000, 82)])
 def test_large_sector_twins(K, N, M, seed):
-    """Sectors of 100 and 166 rows, split into row tiles of <= 96 (96 + 4 and
-    96 + 70): both row buckets of the slice kernel (<= 80 and 81..96 rows) do
-    work, FP64 and FP32."""
+    """Sectors of 100 and 166 rows run whole on the tall kernel (97..320 rows,
+    U shared through LDS); the shorter blocks run on the slice kernel's row
+    buckets; FP64 and FP32 against the oracle."""
     import torch
     d = _lib()
     p = synth.make_problem(K, N, 0, M, seed)
@@ -213,8 +213,8 @@ def test_large_sector_twins(K, N, M, seed):
     torch.cuda.synchronize()
     _close(H, L, R, ctx)
     work = {k & 255: fl for k, _, fl in launches}
-    assert any(work[k] > 0 for k in range(0, 6)), work
-    assert any(work[k] > 0 for k in range(6, 12)), work
+    assert any(work[k] > 0 for k in range(16, 22)), work
+    assert any(work[k] > 0 for k in range(0, 12)), work
     e64, e32 = _rel(got, ref), _rel(got32, ref)
     print(f"[gpu] twin K={K} M={M} f64={e64:.2e} f32={e32:.2e}", flush=True)
     assert e64 <= 1e-12
@@ -322,3 +322,160 @@ def test_mixed_vs_fp64_eight_roots():
         es[prec] = np.sort(e)
     _close(H, L, R, ctx)
     assert np.abs(es[0] - es[1]).max() <= 1e-8, (es[0], es[1])
+
+
+@pytest.mark.parametrize("scheme", ["CN", "NC"])
+def test_forced_small_growth_batches_and_family_chunks(scheme, monkeypatch):
+    """The bounded-memory paths of the build, forced at a small size: every
+    growth step forms and consumes its integral-weighted temporaries one
+    operator at a time (DMRG_GROW_BATCH_BYTES=1), every family sum over the
+    operator index is cut into chunks of two operators (DMRG_FAMILY_CHUNK_OPS=2,
+    the path that keeps each operand's span below 2^32 bytes at large sizes),
+    and blocks of more than 8 rows transform in two passes (the path of the
+    large sectors near the edges).  The product must still equal the oracle's
+    to 1e-12."""
+    monkeypatch.setenv("DMRG_GROW_BATCH_BYTES", "1")
+    monkeypatch.setenv("DMRG_FAMILY_CHUNK_OPS", "2")
+    # blocks of more than 8 new rows transform in two passes (temporaries, then U^T T)
+    monkeypatch.setenv("DMRG_TWO_PASS_ROWS", "8")
+    p = synth.make_problem(10, 10, 0, 30, 23, n_proc=3, proc_id=2) if scheme == "NC" else \
+        synth.make_problem(10, 9, 1, 30, 24)
+    if scheme == "NC":
+        hp, gp = share.masked_integrals(p.h1e, p.g2e, 3, 2)
+        ref = blockops.MiddleHeff(p, "NC", hp, gp).apply(p.psi)
+    else:
+        ref = blockops.MiddleHeff(p, "CN").apply(p.psi)
+    ctx, L, R, H, keep = _step(p, scheme)
+    got = _apply(H, p.psi)
+    got32 = _apply(H, p.psi, _lib().DMRG_PREC_F32)
+    _close(H, L, R, ctx)
+    assert _rel(got, ref) <= 1e-12
+    assert _rel(got32, ref) <= 1e-5
+
+
+def test_caller_layout_and_fp64_only():
+    """dmrg_heff_create with a caller's wavefunction layout (sub-blocks in
+    reverse order): the product is the default one with its sub-blocks moved;
+    an H_eff created for FP64 only refuses FP32 products."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(10, 10, 0, 30, 25)
+    ctx, L, R, H, keep = _step(p)
+    lay = H.psi_layout()
+    assert sum(r * c for (_, _, _, _, r, c, _) in lay) == H.dim
+    # reversed order, contiguous
+    perm, off = [], 0
+    for (ql, s1, s2, qr, r, c, o) in reversed(lay):
+        perm.append((ql, s1, s2, off, o, r * c))
+        off += r * c
+    H2 = ctx.heff_create(L, R, 1, d.DMRG_PREC_F64, [(ql, s1, s2, no) for (ql, s1, s2, no, _, _) in perm])
+    x = np.zeros(H.dim)
+    for (ql, s1, s2, no, o, n) in perm:
+        x[no:no + n] = p.psi[o:o + n]
+    got = _apply(H2, x)
+    ref = _apply(H, p.psi)
+    back = np.zeros(H.dim)
+    for (ql, s1, s2, no, o, n) in perm:
+        back[o:o + n] = got[no:no + n]
+    assert np.array_equal(back, ref)
+    xin = torch.from_numpy(x.astype(np.float32)).cuda()
+    with pytest.raises(d.DmrgError):
+        H2.apply(xin, torch.empty_like(xin), d.DMRG_PREC_F32)
+    bad = [(ql, s1, s2, no + 1) for (ql, s1, s2, no, _, _) in perm]
+    with pytest.raises(d.DmrgError):
+        ctx.heff_create(L, R, 1, d.DMRG_PREC_F64, bad)
+    _close(H2, H, L, R, ctx)
+
+
+def test_renormalize_opset_and_stepping_davidson():
+    """dmrg_renormalize grows any block by its next site (here Lb by d1) and
+    equals the H_eff-based transformation and the oracle; the Davidson solve
+    run one iteration at a time equals the one-call solve."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(10, 10, 0, 30, 48)
+    ctx, L, R, H, keep = _step(p)
+    iso = d.Isometry(p.next_iso, torch.device("cuda:0"))
+    N1 = H.renormalize(iso)
+    N2 = ctx.renormalize(L, iso)
+    ref = blockops.MiddleHeff(p, "CN").renormalize_left()
+    worst = 0.0
+    for key, op in ref.ops.items():
+        kind = key[0]
+        pp = key[1] if len(key) > 1 else -1
+        qq = key[2] if len(key) > 2 else -1
+        for qk, blk in op.blocks.items():
+            a = N1.block(kind, pp, qq, qk, blk.shape)
+            b = N2.block(kind, pp, qq, qk, blk.shape)
+            worst = max(worst, float(np.abs(a - blk).max()), float(np.abs(b - blk).max()))
+    psi = torch.from_numpy(p.psi.copy()).cuda()
+    e1, st1 = H.davidson(psi.clone(), 1, tol=1e-7, precision=d.DMRG_PREC_F32)
+    solve = H.davidson_start(psi.clone(), 1, tol=1e-7, precision=d.DMRG_PREC_F32)
+    n = 0
+    while True:
+        done, ritz, res = solve.step()
+        n += 1
+        if done:
+            break
+        assert n < 400
+    out = torch.empty_like(psi)
+    e2, st2 = solve.finish(out)
+    solve.free()
+    _close(N1, N2, H, L, R, ctx)
+    assert worst <= 1e-12
+    assert st1["iters"] == st2["iters"] and st2["converged"] == 1
+    assert abs(e1[0] - e2[0]) <= 1e-12
+
+
+def test_workspace_queries_are_exact():
+    """Each stage's dmrg_query_workspace (host only) gives the arena size it
+    needs: the whole middle step runs in an arena of exactly the largest
+    answer, and fails with DMRG_E_WORKSPACE in one 4 KiB smaller."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(12, 12, 0, 60, 26)
+
+    def run(arena, record=None):
+        ctx = d.Context(arena)
+        n_elec = p.target[0] + p.target[1]
+        ctx.set_integrals(p.h1e, p.g2e, n_elec, p.target[0] - p.target[1])
+        li = [d.Isometry(u, ctx.device) for u in p.left_iso]
+        ri = [d.Isometry(u, ctx.device) for u in p.right_iso]
+        objs = []
+        try:
+            def q(what, args):
+                if record is not None:
+                    record.append(d.query_workspace(ctx, what, args))
+            arr = (d.Bsm * len(li))(*[i.bsm for i in li])
+            q(d.DMRG_WS_BLOCK, d.WsBlock(0, 0, 0, 1, 1, d.DMRG_LEFT, len(li), d.DMRG_SCHEME_NC, arr))
+            L = ctx.build_block(d.DMRG_LEFT, li, d.DMRG_SCHEME_NC)
+            objs.append(L)
+            arr = (d.Bsm * len(ri))(*[i.bsm for i in ri])
+            q(d.DMRG_WS_BLOCK, d.WsBlock(0, 0, 0, 1, 1, d.DMRG_RIGHT, len(ri), d.DMRG_SCHEME_CN, arr))
+            R = ctx.build_block(d.DMRG_RIGHT, ri, d.DMRG_SCHEME_CN)
+            objs.append(R)
+            q(d.DMRG_WS_TRANSFORM, d.WsTransform(R.ptr))
+            ctx.normal_to_complementary(R)
+            q(d.DMRG_WS_HEFF, d.WsHeff(L.ptr, R.ptr, 1, d.DMRG_PREC_F32))
+            H = ctx.heff_create(L, R, 1, d.DMRG_PREC_F32)
+            objs.append(H)
+            opts = d.DavOpts(3, 24, 1e-6, d.DMRG_PREC_F32, 1e-4, 3, 0.0)
+            q(d.DMRG_WS_DAVIDSON, d.WsDavidson(H.dim, 1, opts))
+            psi = torch.from_numpy(p.psi.copy()).cuda()
+            H.davidson(psi, 1, precision=d.DMRG_PREC_F32, fixed_iters=3)
+            torch.cuda.synchronize()
+            return True
+        except d.DmrgError as e:
+            assert e.status == -3, e   # DMRG_E_WORKSPACE
+            return False
+        finally:
+            for o in reversed(objs):
+                o.free()
+            ctx.close()
+
+    rec = []
+    assert run(1 << 30, rec)
+    need = max(rec)
+    print(f"[gpu] workspace per stage {rec} -> {need}", flush=True)
+    assert run(need)
+    assert not run(need - 4096)
