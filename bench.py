@@ -146,7 +146,8 @@ def main():
     ap.add_argument("--converge", action="store_true",
                     help="also run both policies to convergence (residual <= 1e-6, at most 300 iterations)")
     ap.add_argument("--profile-apply", type=int, default=0,
-                    help="only build once and run this many FP32 and FP64 products (for profilers)")
+                    help="only build once and run this many FP32 and FP64 products (for profilers); with "
+                         "DMRG_TUNE_CACHE naming the cache a previous run wrote, no tuning products run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU (sub-Hamiltonian) path is not part of this build",
@@ -197,7 +198,6 @@ def main():
         arr = (dmrg.Bsm * len(isos))(*[i.bsm for i in isos])
         return dmrg.query_workspace(ctx, dmrg.DMRG_WS_BLOCK, dmrg.WsBlock(0, 0, 0, 1, 1, side, len(isos), sch, arr))
 
-    t_build = time.perf_counter()
     timed("integrals", lambda: ctx.set_integrals(prob.h1e, prob.g2e, n_elec, two_sz, prob.e_core, prob.n_proc,
                                                  prob.proc_id))
     need["left"] = ws_block(dmrg.DMRG_LEFT, li, dmrg.DMRG_SCHEME_NC)
@@ -209,8 +209,11 @@ def main():
         need["transform"] = dmrg.query_workspace(ctx, dmrg.DMRG_WS_TRANSFORM, dmrg.WsTransform(R.ptr))
         timed("middle_transform", lambda: ctx.normal_to_complementary(R))
     need["heff"] = dmrg.query_workspace(ctx, dmrg.DMRG_WS_HEFF, dmrg.WsHeff(L.ptr, R.ptr, roots, dmrg.DMRG_PREC_F32))
-    H = timed("heff_create", lambda: ctx.heff_create(L, R, roots, dmrg.DMRG_PREC_F32))
-    ms_build = (time.perf_counter() - t_build) * 1e3
+    # products replay a graph of their launches; the work list's parameters are
+    # chosen by timing candidates (the autotuner), its choice reported below
+    flags = dmrg.DMRG_HEFF_AUTOTUNE | (0 if args.profile_apply else dmrg.DMRG_HEFF_GRAPH)
+    H = timed("heff_create", lambda: ctx.heff_create(L, R, roots, dmrg.DMRG_PREC_F32, flags=flags))
+    ms_build = sum(stages.values())
     dav_kw = dict(max_subspace=max(24, 4 * roots))
     opts = dmrg.DavOpts(300, dav_kw["max_subspace"], 1e-6, dmrg.DMRG_PREC_F32, 1e-4, 0, 0.0)
     need["davidson"] = dmrg.query_workspace(ctx, dmrg.DMRG_WS_DAVIDSON, dmrg.WsDavidson(dim, roots, opts))
@@ -340,6 +343,7 @@ def main():
         "arena_needed_bytes": need,
         "arena_peak_gb": round(ctx.arena_peak / 2**30, 2),
         "terms_2idx_1idx_H": H.terms(),
+        "heff": H.info(),
         "roofline": roofline(launches, F, args.workload),
         "launches_f32": [{"kernel": launch_kernel_name(k), "ms": round(ms, 3), "useful_tflop": round(fl / 1e12, 4)}
                          for k, ms, fl in launches if ms > 0],

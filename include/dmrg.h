@@ -183,13 +183,40 @@ typedef struct {
  *              partial-tile buffer is sized for it);
  *   precision: DMRG_PREC_F64 -- FP64 products only; DMRG_PREC_F32 -- FP32
  *              products as well (the FP32-mixed policy): the operators are
- *              rounded to binary32 copies here, once.
+ *              rounded to binary32 copies here, once;
+ *   flags:     DMRG_HEFF_GRAPH -- every product (dmrg_heff_apply, and so
+ *              Davidson) replays a graph of its kernel launches, instantiated
+ *              once per precision and vector batch, with the nodes' vector
+ *              arguments updated per call;  DMRG_HEFF_AUTOTUNE (needs
+ *              DMRG_PREC_F32) -- the work list's parameters (the number of
+ *              equal-cost chunks heavy tiles are cut into, and the height
+ *              from which tiles run on the tall kernel) are chosen by timing
+ *              one FP32 product of each candidate, then cached for the shape
+ *              (the file named by DMRG_TUNE_CACHE, if set, keeps the cache
+ *              across processes).  dmrg_heff_get_info reports the choice.
  * DMRG_E_ARG for a layout that does not match the blocks; DMRG_E_WORKSPACE if
  * the arena cannot hold the blocked operators, lists and copies. */
+enum { DMRG_HEFF_GRAPH = 1,      /* products replay a graph of their kernel launches */
+       DMRG_HEFF_AUTOTUNE = 2 };  /* time candidate work lists at creation, keep the fastest */
 dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right,
                              const dmrg_psi_layout* layout, int32_t n_roots, int32_t precision,
-                             dmrg_heff** out, void* stream);
+                             int32_t flags, dmrg_heff** out, void* stream);
 int64_t dmrg_heff_dim(const dmrg_heff* H);
+typedef struct {
+    int32_t flags;                /* as created */
+    int32_t balance_target;       /* equal-cost chunks the work is cut into */
+    int32_t tall_min_rows;        /* tiles of this many rows or more run on the tall kernel */
+    int32_t tuned;                /* 0 defaults, 1 timed at creation, 2 from the cache */
+    int32_t n_candidates;         /* candidates timed (tuned == 1), at most 8 */
+    float candidate_ms[8];        /* FP32 product time of each */
+    int32_t candidate_balance[8];
+    int32_t candidate_tall_min[8];
+    int32_t graphs;               /* product graphs instantiated */
+    int64_t graph_launches;       /* products run as graph replays */
+    int64_t tasks;                /* output tiles of the work list */
+    int32_t reductions;           /* split tiles summed by the reduction */
+} dmrg_heff_info;
+dmrg_status dmrg_heff_get_info(const dmrg_heff* H, dmrg_heff_info* info);
 /* Readback of the layout in use (host arrays of capacity >= n, any may be
  * NULL): qn_left / qn_right [2 n], site1 / site2 [n], rows / cols / offset
  * [n].  Returns the number of sub-blocks. */

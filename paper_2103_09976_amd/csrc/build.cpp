@@ -1083,7 +1083,7 @@ dmrg_status dmrg_query_workspace(const dmrg_ctx* cctx, int32_t what, const void*
         case DMRG_WS_HEFF: {
             const dmrg_ws_heff* a = (const dmrg_ws_heff*)args;
             dmrg_heff* H = nullptr;
-            st = dmrg_heff_create(ctx, a->left, a->right, nullptr, a->n_roots, a->precision, &H, nullptr);
+            st = dmrg_heff_create(ctx, a->left, a->right, nullptr, a->n_roots, a->precision, 0, &H, nullptr);
             dmrg_heff_free(H);
             break;
         }

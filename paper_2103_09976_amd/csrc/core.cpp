@@ -401,7 +401,16 @@ size_t WorkList::ntasks() const {
 int task_class_of(const WorkList& w, const dmrgk::Task& t) {
     int rows = t.m;
     for (int g = t.g0; g < t.g1; ++g) rows = std::max(rows, w.groups[g].mu);
-    return dmrgk::task_class(rows, t.ncol);
+    return dmrgk::task_class(rows, t.ncol, w.tall_min);
+}
+
+void reclassify(WorkList& w) {
+    std::vector<dmrgk::Task> all;
+    for (auto& T : w.task) {
+        all.insert(all.end(), T.begin(), T.end());
+        T.clear();
+    }
+    for (const dmrgk::Task& t : all) w.task[task_class_of(w, t)].push_back(t);
 }
 
 void emit_block_tasks(WorkList& w, int cbuf, int64_t c_off, int ldc, int m, int n, int g0, int g1,
@@ -502,7 +511,7 @@ void split_large(WorkList& w) {
             u.g1 = it->second.second;
             int rows = u.m;
             for (int g = u.g0; g < u.g1; ++g) rows = std::max(rows, ng[g].mu);
-            w.task[dmrgk::task_class(rows, u.ncol)].push_back(u);
+            w.task[dmrgk::task_class(rows, u.ncol, w.tall_min)].push_back(u);
         }
     }
     w.groups.swap(ng);

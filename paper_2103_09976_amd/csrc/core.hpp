@@ -231,6 +231,7 @@ struct WorkList {
     std::vector<dmrgk::Contrib> contribs;
     std::vector<dmrgk::Reduce> reduces;   // sums of split tasks' partial tiles
     int64_t partial_elems = 0;            // per-vector size of the partial buffer
+    int tall_min = dmrgk::kMaxRows + 1;   // tiles of this many rows or more run on the tall kernel
     void clear();
     size_t ntasks() const;
 };
@@ -264,6 +265,8 @@ void split_large(WorkList& w);
 // 1/target_tasks of the total cost each (chunks write partial tiles that a
 // reduction sums in fixed order), then orders every class by decreasing cost.
 void balance_work(WorkList& w, int target_tasks);
+// re-sorts every task into its class under w.tall_min
+void reclassify(WorkList& w);
 double task_cost(const WorkList& w, const dmrgk::Task& t);
 // the task's records fit the LDS staging (kRecG groups, kRecC contiguous contributions)
 bool records_fit(const WorkList& w, const dmrgk::Task& t);

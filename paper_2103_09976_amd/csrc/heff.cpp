@@ -22,6 +22,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <thread>
+#include <deque>
+#include <fstream>
+#include <memory>
+#include <mutex>
+#include <sstream>
 #include <unordered_set>
 
 #include "core.hpp"
@@ -38,16 +43,27 @@ struct PhaseClock {
     }
 };
 
-// Number of equal-cost chunks the H_eff work is cut into (tasks above
-// total/target are split): enough for many resident waves per compute unit
-// (the small-tile kernels hide latency by occupancy) and a short last wave
-// of each launch.  DMRG_BALANCE overrides it.
-static int balance_target() {
-    const char* e = std::getenv("DMRG_BALANCE");
-    return e ? std::atoi(e) : 131072;
-}
 
 using namespace dmrg;
+
+// Parameters of the work list that the autotuner chooses: the number of
+// equal-cost chunks heavy tasks are cut into, and the height from which tiles
+// run on the tall kernel (97: only tiles the one-wave kernels cannot hold).
+struct TuneParams {
+    int balance = 131072;
+    int tall_min = dmrgk::kMaxRows + 1;
+};
+
+// A product captured as a graph of kernel nodes (one per non-empty class,
+// then the reduction), replayed with its nodes' arguments updated to the
+// vectors of each call.
+struct ProductGraph {
+    int prec = -1, nvec = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> nodes;
+    std::vector<int> cls;   // class of each node; dmrgk::kNumClass is the reduction
+};
 
 struct PsiBlock {
     int a, s1, s2, b;
@@ -90,6 +106,17 @@ struct dmrg_heff {
     size_t ntask = 0, ngroup = 0, ncontrib = 0;
     int precision = DMRG_PREC_F32;      // DMRG_PREC_F64: FP64 products only
     const dmrg_psi_layout* layout = nullptr;   // caller's layout during creation (NULL: default)
+    int flags = 0;                      // DMRG_HEFF_GRAPH | DMRG_HEFF_AUTOTUNE
+    // work-list parameters (defaults, tuned or cached) and the tuning record
+    TuneParams tune;
+    int tuned = 0;
+    std::vector<TuneParams> cand;
+    std::vector<float> cand_ms;
+    std::unique_ptr<WorkList> base;     // the list before splitting, kept while tuning
+    int64_t buf_elems[dmrgk::kMaxBuf] = {0};
+    // captured products: one graph per (precision, vector batch)
+    std::deque<ProductGraph> graphs;
+    int64_t graph_launches = 0;
 };
 
 namespace dmrg {
@@ -263,6 +290,77 @@ static int buf_of(const dmrg_heff* H, const OpSetImpl* s) {
 }
 
 }  // namespace dmrg
+
+// Splits, balances and checks a work list under the given parameters.
+static dmrg_status finalize_list(dmrg_heff* H, WorkList& wl, const TuneParams& tp) {
+    wl.tall_min = tp.tall_min;
+    reclassify(wl);
+    split_large(wl);
+    balance_work(wl, tp.balance);
+    int64_t sz[dmrgk::kMaxBuf];
+    for (int i = 0; i < dmrgk::kMaxBuf; ++i) sz[i] = H->buf_elems[i];
+    sz[dmrgk::kPartialBuf] = wl.partial_elems;
+    return validate_work(wl, sz);
+}
+
+// Shape key of an H_eff for the tuning cache: orbitals, electrons, share,
+// roots and every sector dimension of both blocks (FNV-1a).
+static std::string shape_key(const dmrg_heff* H) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t x) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (uint64_t)((x >> (8 * i)) & 255);
+            h *= 1099511628211ull;
+        }
+    };
+    const Ctx* C = H->ctx;
+    mix(C->K); mix(C->na); mix(C->nb); mix(C->n_proc); mix(C->proc_id); mix(H->n_roots);
+    for (const OpSetImpl* S : {H->Lb, H->Rb})
+        for (int i = 0; i < S->basis.size(); ++i) {
+            mix(S->basis.q[i].a);
+            mix(S->basis.q[i].b);
+            mix(S->basis.m[i]);
+        }
+    char buf[32];
+    std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+    return buf;
+}
+
+// Process-wide tuning cache; DMRG_TUNE_CACHE names a file that is read once
+// and appended to ("key balance tall_min" per line).
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneParams> g_tune;
+static bool g_tune_loaded = false;
+
+static void lookup_tuning(dmrg_heff* H) {
+    H->tune = TuneParams();
+    if (const char* e = std::getenv("DMRG_BALANCE")) H->tune.balance = std::max(1, std::atoi(e));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) {
+        g_tune_loaded = true;
+        if (const char* f = std::getenv("DMRG_TUNE_CACHE")) {
+            std::ifstream in(f);
+            std::string key;
+            TuneParams tp;
+            while (in >> key >> tp.balance >> tp.tall_min) g_tune[key] = tp;
+        }
+    }
+    auto it = g_tune.find(shape_key(H));
+    if (it != g_tune.end()) {
+        H->tune = it->second;
+        H->tuned = 2;
+    }
+}
+
+static void store_tuning(const dmrg_heff* H) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const std::string key = shape_key(H);
+    g_tune[key] = H->tune;
+    if (const char* f = std::getenv("DMRG_TUNE_CACHE")) {
+        std::ofstream out(f, std::ios::app);
+        out << key << " " << H->tune.balance << " " << H->tune.tall_min << "\n";
+    }
+}
 
 // The caller's wavefunction layout: every sub-block (a, s1, s2) once, tiling
 // [0, dim) exactly; the offsets replace the default ones.
@@ -661,10 +759,10 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         sz[5] = H->TR.elems;
         sz[6] = H->TML.elems;
         sz[7] = H->TMR.elems;
-        split_large(wl);
-        balance_work(wl, balance_target());
-        sz[dmrgk::kPartialBuf] = wl.partial_elems;
-        dmrg_status vs = validate_work(wl, sz);
+        for (int i = 0; i < dmrgk::kMaxBuf; ++i) H->buf_elems[i] = sz[i];
+        if (H->flags & DMRG_HEFF_AUTOTUNE) H->base.reset(new WorkList(wl));
+        lookup_tuning(H);
+        dmrg_status vs = finalize_list(H, wl, H->tune);
         if (vs != DMRG_OK) return vs;
         for (const auto& d : dtm) {
             if (d.x_off >= 0 && (d.xbuf < 0 || d.xbuf >= 8 || d.x_off >= sz[d.xbuf])) return fail(DMRG_E_STATE, "diag X");
@@ -757,6 +855,198 @@ static dmrg_status ensure_f32(dmrg_heff* H, void* stream) {
     return DMRG_OK;
 }
 
+static dmrgk::Bases<float> bases32(const dmrg_heff* H) {
+    dmrgk::Bases<float> b{};
+    for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
+    b.p[dmrgk::kPartialBuf] = H->part ? (float*)H->part : H->f32[0];
+    b.vstride[dmrgk::kPartialBuf] = H->part_elems;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// graph replay of a product: the class launches and the reduction as kernel
+// nodes in launch order; each call rewrites the nodes' arguments (the vector
+// pointers) and launches the instantiated graph on the caller's stream
+template <typename T>
+static hipKernelNodeParams node_params(const dmrgk::KernelDesc& kd, void** args) {
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(kd.func);
+    p.gridDim = dim3(kd.gx, kd.gy);
+    p.blockDim = dim3(kd.bx);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    return p;
+}
+
+template <typename T>
+static dmrg_status run_graph(dmrg_heff* H, int prec, const dmrgk::Bases<T>& b, int nvec, void* stream) {
+    const DevWork& d = H->work;
+    constexpr bool f64 = sizeof(T) == 8;
+    ProductGraph* pg = nullptr;
+    for (ProductGraph& g : H->graphs)
+        if (g.prec == prec && g.nvec == nvec) pg = &g;
+    auto chain = [&](int c) {
+        return f64 ? dmrgk::chain_desc_f64(c, d.lds_records, d.ntask[c], nvec)
+                   : dmrgk::chain_desc_f32(c, d.lds_records, d.ntask[c], nvec);
+    };
+    auto reduce = [&]() { return f64 ? dmrgk::reduce_desc_f64(d.nred, nvec) : dmrgk::reduce_desc_f32(d.nred, nvec); };
+    if (!pg) {
+        H->graphs.emplace_back();
+        pg = &H->graphs.back();
+        pg->prec = prec;
+        pg->nvec = nvec;
+        DMRG_HIP(hipGraphCreate(&pg->graph, 0));
+        hipGraphNode_t prev = nullptr;
+        for (int c = dmrgk::kNumClass - 1; c >= 0; --c) {
+            if (d.ntask[c] == 0) continue;
+            const dmrgk::KernelDesc kd = chain(c);
+            dmrgk::ChainArgs<T> a(b, d.task[c], d.ntask[c], d.groups, d.contribs, nvec);
+            const hipKernelNodeParams p = node_params<T>(kd, a.ptrs);
+            hipGraphNode_t n;
+            DMRG_HIP(hipGraphAddKernelNode(&n, pg->graph, prev ? &prev : nullptr, prev ? 1 : 0, &p));
+            pg->nodes.push_back(n);
+            pg->cls.push_back(c);
+            prev = n;
+        }
+        if (d.nred > 0) {
+            dmrgk::ReduceArgs<T> a(d.reduces, b);
+            const hipKernelNodeParams p = node_params<T>(reduce(), a.ptrs);
+            hipGraphNode_t n;
+            DMRG_HIP(hipGraphAddKernelNode(&n, pg->graph, prev ? &prev : nullptr, prev ? 1 : 0, &p));
+            pg->nodes.push_back(n);
+            pg->cls.push_back(dmrgk::kNumClass);
+        }
+        if (pg->nodes.empty()) return DMRG_OK;
+        DMRG_HIP(hipGraphInstantiate(&pg->exec, pg->graph, nullptr, nullptr, 0));
+    } else {
+        for (size_t i = 0; i < pg->nodes.size(); ++i) {
+            const int c = pg->cls[i];
+            if (c < dmrgk::kNumClass) {
+                dmrgk::ChainArgs<T> a(b, d.task[c], d.ntask[c], d.groups, d.contribs, nvec);
+                const hipKernelNodeParams p = node_params<T>(chain(c), a.ptrs);
+                DMRG_HIP(hipGraphExecKernelNodeSetParams(pg->exec, pg->nodes[i], &p));
+            } else {
+                dmrgk::ReduceArgs<T> a(d.reduces, b);
+                const hipKernelNodeParams p = node_params<T>(reduce(), a.ptrs);
+                DMRG_HIP(hipGraphExecKernelNodeSetParams(pg->exec, pg->nodes[i], &p));
+            }
+        }
+    }
+    if (!pg->exec) return DMRG_OK;
+    DMRG_HIP(hipGraphLaunch(pg->exec, (hipStream_t)stream));
+    ++H->graph_launches;
+    return DMRG_OK;
+}
+
+static void drop_graphs(dmrg_heff* H) {
+    for (ProductGraph& g : H->graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        if (g.graph) hipGraphDestroy(g.graph);
+    }
+    H->graphs.clear();
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: every candidate work list (balance target x tall threshold) is
+// built, uploaded and timed on one FP32 product of zero vectors (the
+// kernels' work does not depend on the values); the fastest is kept and
+// cached under the H_eff's shape key
+static dmrg_status autotune(dmrg_heff* H, void* stream) {
+    Ctx* C = H->ctx;
+    hipStream_t s = (hipStream_t)stream;
+    bool mid = false;   // tiles of 81..96 rows exist, so the tall threshold matters
+    for (const auto& T : H->base->task)
+        for (const dmrgk::Task& t : T) {
+            int rows = t.m;
+            for (int g = t.g0; g < t.g1; ++g) rows = std::max(rows, H->base->groups[g].mu);
+            if (rows > dmrgk::kShortRows && rows <= dmrgk::kMaxRows) mid = true;
+        }
+    H->cand.clear();
+    for (int bal : {65536, 131072, 262144}) {
+        H->cand.push_back(TuneParams{bal, dmrgk::kMaxRows + 1});
+        if (mid) H->cand.push_back(TuneParams{bal, dmrgk::kShortRows + 1});
+    }
+    // the current list and its partial tiles make room for the candidates
+    free_work(C, H->work);
+    if (H->part_region >= 0) C->arena.release(H->part_region);
+    H->part_region = -1;
+    H->part = nullptr;
+    const int64_t vreg = C->arena.alloc(H->dim * 4 * 2);
+    if (vreg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's vectors");
+    float* x = (float*)(C->arena.base + vreg);
+    float* y = x + H->dim;
+    if (!C->dry) DMRG_HIP(hipMemsetAsync(x, 0, H->dim * 4 * 2, s));
+    H->cand_ms.assign(H->cand.size(), 0.f);
+    hipEvent_t e0, e1;
+    DMRG_HIP(hipEventCreate(&e0));
+    DMRG_HIP(hipEventCreate(&e1));
+    dmrg_status st = DMRG_OK;
+    size_t best = 0;
+    int64_t biggest = 0;
+    for (size_t k = 0; k < H->cand.size() && st == DMRG_OK; ++k) {
+        WorkList w = *H->base;
+        st = finalize_list(H, w, H->cand[k]);
+        DevWork dw;
+        int64_t preg = -1;
+        if (st == DMRG_OK) st = upload_work(C, w, dw, stream);
+        if (st == DMRG_OK && w.partial_elems > 0) {
+            preg = C->arena.alloc(w.partial_elems * 4);
+            if (preg < 0) st = fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's partial tiles");
+        }
+        biggest = std::max(biggest, work_bytes(w) + w.partial_elems * 8 * H->n_roots);
+        if (st == DMRG_OK && !C->dry) {
+            dmrgk::Bases<float> b = bases32(H);
+            b.p[dmrgk::kPartialBuf] = preg >= 0 ? (float*)(C->arena.base + preg) : H->f32[0];
+            b.vstride[dmrgk::kPartialBuf] = w.partial_elems;
+            b.p[2] = x;
+            b.p[3] = y;
+            st = run_work_f32(dw, b, 1, stream);   // warm-up
+            float best_ms = 1e30f;
+            for (int r = 0; r < 2 && st == DMRG_OK; ++r) {
+                hipEventRecord(e0, s);
+                st = run_work_f32(dw, b, 1, stream);
+                hipEventRecord(e1, s);
+                if (st == DMRG_OK && hipEventSynchronize(e1) != hipSuccess) st = fail(DMRG_E_HIP, "autotune timing");
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                best_ms = std::min(best_ms, ms);
+            }
+            H->cand_ms[k] = best_ms;
+            if (best_ms < H->cand_ms[best]) best = k;
+        }
+        free_work(C, dw);
+        if (preg >= 0) C->arena.release(preg);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    C->arena.release(vreg);
+    if (st != DMRG_OK) return st;
+    if (C->dry) {
+        // the choice is made on the device; size the rebuild for the largest candidate
+        for (size_t k = 0; k < H->cand.size(); ++k) {
+            WorkList w = *H->base;
+            finalize_list(H, w, H->cand[k]);
+            if (work_bytes(w) + w.partial_elems * 8 * H->n_roots == biggest) best = k;
+        }
+    }
+    H->tune = H->cand[best];
+    H->tuned = 1;
+    WorkList w = *H->base;
+    H->base.reset();
+    st = finalize_list(H, w, H->tune);
+    if (st != DMRG_OK) return st;
+    H->part_elems = w.partial_elems;
+    if (H->part_elems > 0) {
+        H->part_region = C->arena.alloc(H->part_elems * 8 * H->n_roots);
+        if (H->part_region < 0) return fail(DMRG_E_WORKSPACE, "arena too small for partial tiles");
+        H->part = C->arena.base + H->part_region;
+    }
+    st = upload_work(C, w, H->work, stream);
+    if (st == DMRG_OK && !C->dry) store_tuning(H);
+    return st;
+}
+
 Ctx* heff_ctx(const dmrg_heff* H) { return H->ctx; }
 
 extern "C" {
@@ -775,12 +1065,15 @@ static dmrg_status check_heff_args(const dmrg_ctx* ctx, const dmrg_opset* left, 
 }
 
 dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right,
-                             const dmrg_psi_layout* layout, int32_t n_roots, int32_t precision, dmrg_heff** out,
-                             void* stream) {
+                             const dmrg_psi_layout* layout, int32_t n_roots, int32_t precision, int32_t flags,
+                             dmrg_heff** out, void* stream) {
     if (!ctx || !left || !right || !out) return fail(DMRG_E_ARG, "null argument");
     *out = nullptr;
     dmrg_status st = check_heff_args(ctx, left, right, n_roots, precision);
     if (st != DMRG_OK) return st;
+    if (flags & ~(DMRG_HEFF_GRAPH | DMRG_HEFF_AUTOTUNE)) return fail(DMRG_E_ARG, "unknown flags");
+    if ((flags & DMRG_HEFF_AUTOTUNE) && precision != DMRG_PREC_F32)
+        return fail(DMRG_E_ARG, "the autotuner times FP32 products: create with DMRG_PREC_F32");
     dmrg_heff* H = new dmrg_heff();
     H->ctx = ctx;
     H->Lb = left;
@@ -788,9 +1081,12 @@ dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_o
     H->n_roots = n_roots;
     H->precision = precision;
     H->layout = layout;
+    H->flags = flags;
     st = build_heff(H, stream);
     H->layout = nullptr;
     if (st == DMRG_OK && precision == DMRG_PREC_F32) st = ensure_f32(H, stream);
+    if (st == DMRG_OK && H->base && H->tuned == 0) st = autotune(H, stream);
+    H->base.reset();
     if (st == DMRG_OK && !ctx->dry) {
         const int e = (int)hipStreamSynchronize((hipStream_t)stream);
         if (e) st = hip_fail(e, "heff create");
@@ -839,37 +1135,59 @@ int32_t dmrg_heff_terms(const dmrg_heff* H, int32_t* n2, int32_t* n1, int32_t* n
     return H->n2 + H->n1 + H->nh;
 }
 
-dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec, const void* psi, void* sigma,
-                            void* stream) {
+}  // extern "C"
+
+// H_eff psi with the partial tiles of split tasks in `partial` (bytes of
+// room: partial_bytes), or in H's own buffer when partial is NULL.  Vectors
+// go in batches of as many as the partial buffer holds (n_roots for H's own).
+dmrg_status heff_apply_impl(dmrg_heff* H, int32_t precision, int32_t n_vec, const void* psi, void* sigma,
+                            void* partial, int64_t partial_bytes, void* stream) {
     if (!H || !psi || !sigma) return fail(DMRG_E_ARG, "null argument");
     if (n_vec < 1 || n_vec > 65535) return fail(DMRG_E_ARG, "bad n_vec");
     if (psi == sigma) return fail(DMRG_E_ARG, "psi and sigma must not alias");
     if (precision != DMRG_PREC_F64 && precision != DMRG_PREC_F32) return fail(DMRG_E_ARG, "bad precision");
-    // vectors go in batches of at most n_roots: the partial-tile buffer holds that many
-    const int batch = H->part_elems > 0 ? H->n_roots : n_vec;
+    const int64_t es = precision == DMRG_PREC_F64 ? 8 : 4;
+    int batch = H->part_elems > 0 ? H->n_roots : n_vec;
+    if (partial && H->part_elems > 0) {
+        const int64_t per_vec = H->part_elems * es;
+        if (per_vec > partial_bytes)
+            return fail(DMRG_E_WORKSPACE, "the split tiles of one product need " + std::to_string(per_vec) +
+                                              " bytes of scratch; the static scratch holds " +
+                                              std::to_string(partial_bytes));
+        batch = (int)std::min<int64_t>(n_vec, partial_bytes / per_vec);
+    }
+    void* part = partial ? partial : H->part;
     for (int v0 = 0; v0 < n_vec; v0 += batch) {
         const int nv = std::min(batch, n_vec - v0);
         dmrg_status st;
         if (precision == DMRG_PREC_F64) {
             dmrgk::Bases<double> b = bases64(H);
+            if (part) b.p[dmrgk::kPartialBuf] = (double*)part;
             b.p[2] = (double*)psi + (int64_t)v0 * H->dim;
             b.p[3] = (double*)sigma + (int64_t)v0 * H->dim;
             b.vstride[2] = b.vstride[3] = H->dim;
-            st = run_work_f64(H->work, b, nv, stream);
+            st = (H->flags & DMRG_HEFF_GRAPH) ? run_graph<double>(H, precision, b, nv, stream)
+                                              : run_work_f64(H->work, b, nv, stream);
         } else {
             if (H->f32_region < 0) return fail(DMRG_E_STATE, "H_eff was created for FP64 products only");
-            dmrgk::Bases<float> b{};
-            for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
-            b.p[dmrgk::kPartialBuf] = H->part ? (float*)H->part : H->f32[0];
-            b.vstride[dmrgk::kPartialBuf] = H->part_elems;
+            dmrgk::Bases<float> b = bases32(H);
+            if (part) b.p[dmrgk::kPartialBuf] = (float*)part;
             b.p[2] = (float*)psi + (int64_t)v0 * H->dim;
             b.p[3] = (float*)sigma + (int64_t)v0 * H->dim;
             b.vstride[2] = b.vstride[3] = H->dim;
-            st = run_work_f32(H->work, b, nv, stream);
+            st = (H->flags & DMRG_HEFF_GRAPH) ? run_graph<float>(H, precision, b, nv, stream)
+                                              : run_work_f32(H->work, b, nv, stream);
         }
         if (st != DMRG_OK) return st;
     }
     return DMRG_OK;
+}
+
+extern "C" {
+
+dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec, const void* psi, void* sigma,
+                            void* stream) {
+    return heff_apply_impl(H, precision, n_vec, psi, sigma, nullptr, 0, stream);
 }
 
 int32_t dmrg_heff_profile(dmrg_heff* H, int32_t precision, const void* psi, void* sigma, int32_t n, float* ms,
@@ -887,10 +1205,7 @@ int32_t dmrg_heff_profile(dmrg_heff* H, int32_t precision, const void* psi, void
         st = run_work_timed_f64(H->work, b, t, stream);
     } else if (precision == DMRG_PREC_F32) {
         if (H->f32_region < 0) return fail(DMRG_E_STATE, "H_eff was created for FP64 products only");
-        dmrgk::Bases<float> b{};
-        for (int i = 0; i < 8; ++i) b.p[i] = H->f32[i] ? H->f32[i] : H->f32[0];
-        b.p[dmrgk::kPartialBuf] = H->part ? (float*)H->part : H->f32[0];
-        b.vstride[dmrgk::kPartialBuf] = H->part_elems;
+        dmrgk::Bases<float> b = bases32(H);
         b.p[2] = (float*)psi;
         b.p[3] = (float*)sigma;
         b.vstride[2] = b.vstride[3] = H->dim;
@@ -935,9 +1250,33 @@ dmrg_status dmrg_heff_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_o
     return DMRG_OK;
 }
 
+dmrg_status dmrg_heff_get_info(const dmrg_heff* H, dmrg_heff_info* info) {
+    if (!H || !info) return fail(DMRG_E_ARG, "null argument");
+    dmrg_heff_info x{};
+    x.flags = H->flags;
+    x.balance_target = H->tune.balance;
+    x.tall_min_rows = H->tune.tall_min;
+    x.tuned = H->tuned;
+    x.n_candidates = (int32_t)std::min<size_t>(H->cand.size(), 8);
+    for (int i = 0; i < x.n_candidates; ++i) {
+        x.candidate_ms[i] = i < (int)H->cand_ms.size() ? H->cand_ms[i] : 0.f;
+        x.candidate_balance[i] = H->cand[i].balance;
+        x.candidate_tall_min[i] = H->cand[i].tall_min;
+    }
+    x.graphs = (int32_t)H->graphs.size();
+    x.graph_launches = H->graph_launches;
+    int64_t nt = 0;
+    for (int c = 0; c < dmrgk::kNumClass; ++c) nt += H->work.ntask[c];
+    x.tasks = nt;
+    x.reductions = H->work.nred;
+    *info = x;
+    return DMRG_OK;
+}
+
 void dmrg_heff_free(dmrg_heff* H) {
     if (!H) return;
     Ctx* C = H->ctx;
+    drop_graphs(H);
     free_work(C, H->work);
     free_set(C, H->TL);
     free_set(C, H->TR);

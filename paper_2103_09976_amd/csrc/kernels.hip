@@ -117,6 +117,27 @@ __device__ inline const T* base_ptr(int buf, int vec) {
     return b->p[buf] + (int64_t)vec * b->vstride[buf];
 }
 
+// Workgroup -> (unit, vector) of a launch over nvec vectors.  Workgroups are
+// dealt to the eight XCDs in turn (linear id mod 8), so the nvec vectors of one
+// unit are made consecutive workgroups of one XCD: the operator blocks they
+// all read are then fetched into that XCD's L2 once and reused, instead of
+// once per vector.  Units are spread over the XCDs as before (unit mod 8); the
+// grid holds ceil(units / 8) * 8 * nvec workgroups and units past the end exit.
+__device__ inline void unit_vec(int nvec, int& unit, int& vec) {
+    const int L = blockIdx.x;
+    if (nvec == 1) {
+        unit = L;
+        vec = 0;
+        return;
+    }
+    const int local = L >> 3;
+    vec = local % nvec;
+    unit = (local / nvec) * 8 + (L & 7);
+}
+inline unsigned grid_units(int units, int nvec) {
+    return nvec == 1 ? (unsigned)units : (unsigned)((units + 7) / 8 * 8 * nvec);
+}
+
 // ---------------------------------------------------------------------------
 // slice_kernel: output tiles of <= 96 rows x 16*NCT columns.  Every wave
 // computes one 16-column slice of a tile on its own, four slices per
@@ -144,24 +165,26 @@ __global__ __launch_bounds__(256, (SliceOcc<T, RT>::waves)) void slice_kernel(Ba
                                                                         const Task* __restrict__ tasks,
                                                                         int ntask,
                                                                         const Group* __restrict__ groups,
-                                                                        const Contrib* __restrict__ contribs) {
+                                                                        const Contrib* __restrict__ contribs,
+                                                                        int nvec) {
     using V4 = typename Mfma<T>::v4;
     __shared__ Group sG[LR ? 4 : 1][LR ? kRecG : 1];
     __shared__ Contrib sC[LR ? 4 : 1][LR ? kRecC : 1];
     (void)Bargs;
 
-    // four slices per workgroup: wave wv takes unit u = 4 blockIdx.x + wv,
+    // four slices per workgroup: wave wv takes unit u = 4 wg + wv,
     // column slice u % NCT of task u / NCT
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
-    const int u = blockIdx.x * 4 + wv;
+    int wg, vec;
+    unit_vec(nvec, wg, vec);
+    const int u = wg * 4 + wv;
     if (u >= ntask * NCT) return;
     const int w = u % NCT;
     const int lr0 = lane & 15;
     const int lk0 = lane >> 4;
     const Task tk = tasks[u / NCT];
-    const int vec = blockIdx.y;
     const int ncv = min(tk.ncol, tk.n - tk.col0);   // valid columns of the tile
     const int nrm = (tk.m + 15) >> 4;                // output row tiles
     Recs<LR> R;
@@ -404,7 +427,8 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
                                                                          const Task* __restrict__ tasks,
                                                                          int ntask,
                                                                          const Group* __restrict__ groups,
-                                                                         const Contrib* __restrict__ contribs) {
+                                                                         const Contrib* __restrict__ contribs,
+                                                                         int nvec) {
     using V4 = typename Mfma<T>::v4;
     constexpr int RW = kTallRows / 64;   // row tiles per wave
     constexpr int LD = TallCfg<T>::ld;
@@ -413,14 +437,15 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
     __shared__ Group sG[LR ? kRecG : 1];
     __shared__ Contrib sC[LR ? kRecC : 1];
     (void)Bargs;
-    (void)ntask;
 
+    int unit, vec;
+    unit_vec(nvec, unit, vec);
+    if (unit >= ntask * NCT) return;         // the whole workgroup: no barrier is reached
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
-    const int w = blockIdx.x % NCT;          // column slice of the task
-    const Task tk = tasks[blockIdx.x / NCT];  // the grid is exactly ntask * NCT workgroups
-    const int vec = blockIdx.y;
+    const int w = unit % NCT;                // column slice of the task
+    const Task tk = tasks[unit / NCT];
     const int lr0 = lane & 15;
     const int lk0 = lane >> 4;
     const int ncv = min(tk.ncol, tk.n - tk.col0);
@@ -645,19 +670,20 @@ template <typename T, int RT, int CT> struct WaveOcc {
 template <typename T, int RT, int CT, bool LR>
 __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(Bases<T> Bargs, const Task* __restrict__ tasks, int ntask,
                                                    const Group* __restrict__ groups,
-                                                   const Contrib* __restrict__ contribs) {
+                                                   const Contrib* __restrict__ contribs, int nvec) {
     using V4 = typename Mfma<T>::v4;
     __shared__ Group sG[LR ? 4 : 1][LR ? kRecG : 1];
     __shared__ Contrib sC[LR ? 4 : 1][LR ? kRecC : 1];
     (void)Bargs;
     const int wv = threadIdx.x >> 6;
-    const int ti = blockIdx.x * 4 + wv;
+    int wg, vec;
+    unit_vec(nvec, wg, vec);
+    const int ti = wg * 4 + wv;
     if (ti >= ntask) return;
     const int lane = threadIdx.x & 63;
     const int lr = lane & 15;
     const int lk = lane >> 4;
     const Task tk = tasks[ti];
-    const int vec = blockIdx.y;
     const int ncv = min(tk.ncol, tk.n - tk.col0);
     Recs<LR> R;
     if constexpr (LR) {   // each wave stages its own task's records; in-order LDS within a wave
@@ -825,62 +851,79 @@ __global__ __launch_bounds__(256, (WaveOcc<T, RT, CT>::waves)) void wave_kernel(
 }
 
 template <typename T, bool LR>
-static int launch_chain_t(int cls, const Task* t, int ntask, const Group* g, const Contrib* c, const Bases<T>& b,
-                          int nvec, hipStream_t s) {
+static const void* chain_func(int cls) {
+    constexpr int RS = kShortRows / 16, RL = kMaxRows / 16;
     if (cls >= kTallClass0) {   // tall classes: one workgroup per column slice
-        const int nct = cls - kTallClass0 + 1;
-        const dim3 grid(ntask * nct, nvec), block(256);
-        switch (nct) {
-            case 1: hipLaunchKernelGGL((tall_kernel<T, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 2: hipLaunchKernelGGL((tall_kernel<T, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 3: hipLaunchKernelGGL((tall_kernel<T, 3, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 4: hipLaunchKernelGGL((tall_kernel<T, 4, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 5: hipLaunchKernelGGL((tall_kernel<T, 5, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 6: hipLaunchKernelGGL((tall_kernel<T, 6, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            default: return (int)hipErrorInvalidValue;
+        switch (cls - kTallClass0 + 1) {
+            case 1: return (const void*)&tall_kernel<T, 1, LR>;
+            case 2: return (const void*)&tall_kernel<T, 2, LR>;
+            case 3: return (const void*)&tall_kernel<T, 3, LR>;
+            case 4: return (const void*)&tall_kernel<T, 4, LR>;
+            case 5: return (const void*)&tall_kernel<T, 5, LR>;
+            case 6: return (const void*)&tall_kernel<T, 6, LR>;
+            default: return nullptr;
         }
-        return (int)hipGetLastError();
     }
     if (cls >= kNumTileClass) {   // wave classes: four tasks per workgroup
-        const dim3 grid((ntask + 3) / 4, nvec), block(256);
         switch (cls - kNumTileClass) {
-            case 0: hipLaunchKernelGGL((wave_kernel<T, 1, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 1: hipLaunchKernelGGL((wave_kernel<T, 1, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 2: hipLaunchKernelGGL((wave_kernel<T, 2, 1, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            case 3: hipLaunchKernelGGL((wave_kernel<T, 2, 2, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-            default: return (int)hipErrorInvalidValue;
+            case 0: return (const void*)&wave_kernel<T, 1, 1, LR>;
+            case 1: return (const void*)&wave_kernel<T, 1, 2, LR>;
+            case 2: return (const void*)&wave_kernel<T, 2, 1, LR>;
+            case 3: return (const void*)&wave_kernel<T, 2, 2, LR>;
+            default: return nullptr;
         }
-        return (int)hipGetLastError();
     }
     // tile classes: four column slices per workgroup; five row tiles for
     // classes below kColClasses, six above
-    constexpr int RS = kShortRows / 16, RL = kMaxRows / 16;
-    const dim3 grid((ntask * (cls % kColClasses + 1) + 3) / 4, nvec), block(256);
     switch (cls) {
-        case 0: hipLaunchKernelGGL((slice_kernel<T, 1, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 1: hipLaunchKernelGGL((slice_kernel<T, 2, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 2: hipLaunchKernelGGL((slice_kernel<T, 3, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 3: hipLaunchKernelGGL((slice_kernel<T, 4, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 4: hipLaunchKernelGGL((slice_kernel<T, 5, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 5: hipLaunchKernelGGL((slice_kernel<T, 6, RS, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 6: hipLaunchKernelGGL((slice_kernel<T, 1, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 7: hipLaunchKernelGGL((slice_kernel<T, 2, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 8: hipLaunchKernelGGL((slice_kernel<T, 3, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 9: hipLaunchKernelGGL((slice_kernel<T, 4, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 10: hipLaunchKernelGGL((slice_kernel<T, 5, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        case 11: hipLaunchKernelGGL((slice_kernel<T, 6, RL, LR>), grid, block, 0, s, b, t, ntask, g, c); break;
-        default: return (int)hipErrorInvalidValue;
+        case 0: return (const void*)&slice_kernel<T, 1, RS, LR>;
+        case 1: return (const void*)&slice_kernel<T, 2, RS, LR>;
+        case 2: return (const void*)&slice_kernel<T, 3, RS, LR>;
+        case 3: return (const void*)&slice_kernel<T, 4, RS, LR>;
+        case 4: return (const void*)&slice_kernel<T, 5, RS, LR>;
+        case 5: return (const void*)&slice_kernel<T, 6, RS, LR>;
+        case 6: return (const void*)&slice_kernel<T, 1, RL, LR>;
+        case 7: return (const void*)&slice_kernel<T, 2, RL, LR>;
+        case 8: return (const void*)&slice_kernel<T, 3, RL, LR>;
+        case 9: return (const void*)&slice_kernel<T, 4, RL, LR>;
+        case 10: return (const void*)&slice_kernel<T, 5, RL, LR>;
+        case 11: return (const void*)&slice_kernel<T, 6, RL, LR>;
+        default: return nullptr;
     }
-    return (int)hipGetLastError();
+}
+
+// workgroups of one vector's launch of class cls
+static int chain_units(int cls, int ntask) {
+    if (cls >= kTallClass0) return ntask * (cls - kTallClass0 + 1);
+    if (cls >= kNumTileClass) return (ntask + 3) / 4;
+    return (ntask * (cls % kColClasses + 1) + 3) / 4;
+}
+
+template <typename T>
+static KernelDesc chain_desc(int cls, bool lds_records, int ntask, int nvec) {
+    KernelDesc d{};
+    if (ntask <= 0 || cls < 0 || cls >= kNumClass) return d;
+    d.func = lds_records ? chain_func<T, true>(cls) : chain_func<T, false>(cls);
+    d.gx = grid_units(chain_units(cls, ntask), nvec);
+    d.gy = 1;
+    d.bx = 256;
+    return d;
+}
+KernelDesc chain_desc_f64(int cls, bool lds_records, int ntask, int nvec) {
+    return chain_desc<double>(cls, lds_records, ntask, nvec);
+}
+KernelDesc chain_desc_f32(int cls, bool lds_records, int ntask, int nvec) {
+    return chain_desc<float>(cls, lds_records, ntask, nvec);
 }
 
 template <typename T>
 static int launch_chain(int cls, bool lds_records, const Task* t, int ntask, const Group* g, const Contrib* c,
                         const Bases<T>& b, int nvec, void* stream) {
     if (ntask <= 0) return 0;
-    hipStream_t s = (hipStream_t)stream;
-    return lds_records ? launch_chain_t<T, true>(cls, t, ntask, g, c, b, nvec, s)
-                       : launch_chain_t<T, false>(cls, t, ntask, g, c, b, nvec, s);
+    const KernelDesc d = chain_desc<T>(cls, lds_records, ntask, nvec);
+    if (!d.func) return (int)hipErrorInvalidValue;
+    ChainArgs<T> a(b, t, ntask, g, c, nvec);
+    return (int)hipLaunchKernel(d.func, dim3(d.gx, d.gy), dim3(d.bx), a.ptrs, 0, (hipStream_t)stream);
 }
 
 int launch_chain_f64(int cls, bool lds_records, const Task* t, int ntask, const Group* g, const Contrib* c,
@@ -937,10 +980,24 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(const Reduce* __res
 }
 
 template <typename T>
+static KernelDesc reduce_desc(int nred, int nvec) {
+    KernelDesc d{};
+    if (nred <= 0) return d;
+    d.func = (const void*)&reduce_kernel<T>;
+    d.gx = (unsigned)nred;
+    d.gy = (unsigned)nvec;
+    d.bx = kRedThreads;
+    return d;
+}
+KernelDesc reduce_desc_f64(int nred, int nvec) { return reduce_desc<double>(nred, nvec); }
+KernelDesc reduce_desc_f32(int nred, int nvec) { return reduce_desc<float>(nred, nvec); }
+
+template <typename T>
 static int launch_reduce(const Reduce* r, int nred, const Bases<T>& b, int nvec, void* stream) {
     if (nred <= 0) return 0;
-    hipLaunchKernelGGL(reduce_kernel<T>, dim3(nred, nvec), dim3(kRedThreads), 0, (hipStream_t)stream, r, b);
-    return (int)hipGetLastError();
+    const KernelDesc d = reduce_desc<T>(nred, nvec);
+    ReduceArgs<T> a(r, b);
+    return (int)hipLaunchKernel(d.func, dim3(d.gx, d.gy), dim3(d.bx), a.ptrs, 0, (hipStream_t)stream);
 }
 int launch_reduce_f64(const Reduce* r, int nred, const Bases<double>& b, int nvec, void* stream) {
     return launch_reduce<double>(r, nred, b, nvec, stream);

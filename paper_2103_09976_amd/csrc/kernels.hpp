@@ -89,9 +89,10 @@ constexpr int kNumTileClass = 2 * kColClasses;
 constexpr int kTallClass0 = kNumTileClass + 4;
 constexpr int kNumClass = kTallClass0 + kColClasses;
 inline int col_class(int ncol) { return (ncol + 15) / 16 - 1; }
-// rows: max of the tile rows and of every group's mu
-inline int task_class(int rows, int ncol) {
-    if (rows > kMaxRows) return kTallClass0 + col_class(ncol);
+// rows: max of the tile rows and of every group's mu; tiles of tall_min rows
+// or more run on the tall kernel (always above kMaxRows)
+inline int task_class(int rows, int ncol, int tall_min = kMaxRows + 1) {
+    if (rows > kMaxRows || (rows >= tall_min && rows > 32)) return kTallClass0 + col_class(ncol);
     if (rows <= 32 && ncol <= 32) return kNumTileClass + ((rows + 15) / 16 - 1) * 2 + (ncol + 15) / 16 - 1;
     return col_class(ncol) + (rows > kShortRows ? kColClasses : 0);
 }
@@ -109,6 +110,42 @@ inline int class_cols(int cls) {
 // kRecC) are contiguous, runs with lds_records = true.
 constexpr int kRecG = 48;
 constexpr int kRecC = 128;
+
+// A kernel launch as data (function, grid, block), for eager launches and for
+// the nodes of a captured product graph.  func == nullptr: nothing to launch.
+struct KernelDesc {
+    const void* func = nullptr;
+    unsigned gx = 0, gy = 0, bx = 0;
+};
+// Argument blocks of the chain kernels (Bases, tasks, ntask, groups,
+// contributions, nvec) and of the reduction (reductions, Bases); ptrs[] is
+// the kernel-parameter array of hipLaunchKernel / a graph kernel node.
+template <typename T>
+struct ChainArgs {
+    Bases<T> b;
+    const Task* t;
+    int ntask;
+    const Group* g;
+    const Contrib* c;
+    int nvec;
+    void* ptrs[6];
+    ChainArgs(const Bases<T>& b_, const Task* t_, int n_, const Group* g_, const Contrib* c_, int v_)
+        : b(b_), t(t_), ntask(n_), g(g_), c(c_), nvec(v_), ptrs{&b, &t, &ntask, &g, &c, &nvec} {}
+    ChainArgs(const ChainArgs&) = delete;
+};
+struct Reduce;
+template <typename T>
+struct ReduceArgs {
+    const Reduce* r;
+    Bases<T> b;
+    void* ptrs[2];
+    ReduceArgs(const Reduce* r_, const Bases<T>& b_) : r(r_), b(b_), ptrs{&r, &b} {}
+    ReduceArgs(const ReduceArgs&) = delete;
+};
+KernelDesc chain_desc_f64(int cls, bool lds_records, int ntask, int nvec);
+KernelDesc chain_desc_f32(int cls, bool lds_records, int ntask, int nvec);
+KernelDesc reduce_desc_f64(int nred, int nvec);
+KernelDesc reduce_desc_f32(int nred, int nvec);
 
 // launchers (return hipError_t as int)
 int launch_chain_f64(int cls, bool lds_records, const Task* t, int ntask, const Group* g, const Contrib* c,

@@ -57,6 +57,15 @@ class PsiLayout(C.Structure):
 
 
 DMRG_WS_BLOCK, DMRG_WS_TRANSFORM, DMRG_WS_HEFF, DMRG_WS_DAVIDSON, DMRG_WS_RENORMALIZE = 0, 1, 2, 3, 4
+DMRG_HEFF_GRAPH, DMRG_HEFF_AUTOTUNE = 1, 2
+
+
+class HeffInfo(C.Structure):
+    _fields_ = [("flags", C.c_int32), ("balance_target", C.c_int32), ("tall_min_rows", C.c_int32),
+                ("tuned", C.c_int32), ("n_candidates", C.c_int32), ("candidate_ms", C.c_float * 8),
+                ("candidate_balance", C.c_int32 * 8), ("candidate_tall_min", C.c_int32 * 8),
+                ("graphs", C.c_int32), ("graph_launches", C.c_int64), ("tasks", C.c_int64),
+                ("reductions", C.c_int32)]
 
 
 class WsBlock(C.Structure):
@@ -97,7 +106,8 @@ _SIGS = {
                                      C.POINTER(C.c_void_p), C.c_void_p]),
     "dmrg_normal_to_complementary": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dmrg_heff_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(PsiLayout), C.c_int32,
-                                     C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+                                     C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    "dmrg_heff_get_info": (C.c_int32, [C.c_void_p, C.POINTER(HeffInfo)]),
     "dmrg_heff_dim": (C.c_int64, [C.c_void_p]),
     "dmrg_heff_psi_layout": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -291,6 +301,18 @@ class Heff:
                                           C.byref(out), _stream(torch)))
         return DavidsonSolve(out, n_roots)
 
+    def info(self) -> dict:
+        """Work-list parameters (tuned or default), tuning record and graph use."""
+        x = HeffInfo()
+        _check(load().dmrg_heff_get_info(self.ptr, C.byref(x)))
+        n = x.n_candidates
+        return {"flags": x.flags, "balance_target": x.balance_target, "tall_min_rows": x.tall_min_rows,
+                "tuned": {0: "default", 1: "timed", 2: "cached"}[x.tuned],
+                "candidates": [{"balance_target": x.candidate_balance[i], "tall_min_rows": x.candidate_tall_min[i],
+                                "ms_f32": round(float(x.candidate_ms[i]), 3)} for i in range(n)],
+                "graphs": x.graphs, "graph_launches": x.graph_launches, "tasks": x.tasks,
+                "reductions": x.reductions}
+
     def psi_layout(self):
         """[(qn_left, s1, s2, qn_right, rows, cols, offset)] of the layout in use."""
         lib = load()
@@ -397,7 +419,7 @@ class Context:
         _check(load().dmrg_normal_to_complementary(self.ptr, right.ptr, _stream(torch)))
 
     def heff_create(self, left: OpSet, right: OpSet, n_roots: int = 1, precision: int = DMRG_PREC_F32,
-                    layout=None) -> Heff:
+                    layout=None, flags: int = 0) -> Heff:
         """layout: None (default order) or a list of (qn_left, s1, s2, offset)."""
         import torch
         out = C.c_void_p()
@@ -408,7 +430,7 @@ class Context:
                          np.array([l[2] for l in layout], np.int32), np.array([l[3] for l in layout], np.int64))
             p = [a.ctypes.data_as(C.POINTER(t)) for a, t in zip(self._lay, (C.c_int32, C.c_int32, C.c_int32, C.c_int64))]
             lay = C.byref(PsiLayout(n, *p))
-        _check(load().dmrg_heff_create(self.ptr, left.ptr, right.ptr, lay, n_roots, precision, C.byref(out),
+        _check(load().dmrg_heff_create(self.ptr, left.ptr, right.ptr, lay, n_roots, precision, flags, C.byref(out),
                                        _stream(torch)))
         return Heff(self, out)
 
@@ -434,7 +456,7 @@ class Context:
 
 
 def middle_step(prob, arena_bytes: int, scheme: Optional[str] = None, n_roots: int = 1,
-                device: int = 0, precision: int = DMRG_PREC_F32):
+                device: int = 0, precision: int = DMRG_PREC_F32, flags: int = 0):
     """Set up one middle-site step of a synthetic problem on the GPU.
 
     Builds both blocks through the problem's isometries, applies the
@@ -453,5 +475,5 @@ def middle_step(prob, arena_bytes: int, scheme: Optional[str] = None, n_roots: i
     R = ctx.build_block(DMRG_RIGHT, ri, DMRG_SCHEME_CN if scheme == "CN" else DMRG_SCHEME_NC)
     if scheme == "CN":
         ctx.normal_to_complementary(R)
-    H = ctx.heff_create(L, R, n_roots, precision)
+    H = ctx.heff_create(L, R, n_roots, precision, flags=flags)
     return ctx, L, R, H, (li, ri)

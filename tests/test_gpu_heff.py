@@ -479,3 +479,62 @@ def test_workspace_queries_are_exact():
     print(f"[gpu] workspace per stage {rec} -> {need}", flush=True)
     assert run(need)
     assert not run(need - 4096)
+
+
+def test_graph_replay_matches_eager():
+    """Products replayed from a graph (DMRG_HEFF_GRAPH) equal the eager
+    launches bitwise, replay after replay, with other device work and host
+    synchronization in between and with the vector pointers changing."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(12, 11, 1, 60, 27)
+    ctx, L, R, H, keep = _step(p, arena=2 << 30, n_roots=2)
+    G = ctx.heff_create(L, R, 2, d.DMRG_PREC_F32, flags=d.DMRG_HEFF_GRAPH)
+    n = H.dim
+    X = torch.from_numpy(synth.random_vectors(n, 3, 31).ravel().copy()).cuda()
+    for prec, dt in ((d.DMRG_PREC_F64, torch.float64), (d.DMRG_PREC_F32, torch.float32)):
+        xs = X.to(dt)
+        ref = torch.empty_like(xs)
+        H.apply(xs, ref, prec, 3)
+        for rep in range(4):
+            out = torch.full_like(xs, float("nan"))
+            off = rep % 2   # alternate between two vector windows
+            xin = torch.roll(xs, shifts=off * n).contiguous() if off else xs
+            G.apply(xin, out, prec, 3)
+            torch.cuda.synchronize()
+            want = torch.roll(ref, shifts=off * n) if off else ref
+            assert torch.equal(out, want), (prec, rep)
+            junk = torch.randn(1 << 20, device="cuda") * 2.0   # unrelated eager work between replays
+            torch.cuda.synchronize()
+            del junk
+    info = G.info()
+    assert info["graphs"] >= 2 and info["graph_launches"] >= 8
+    _close(G, H, L, R, ctx)
+
+
+def test_autotune_choice_cache_and_parity(monkeypatch, tmp_path):
+    """DMRG_HEFF_AUTOTUNE times every candidate work list and keeps the
+    fastest; the product still matches the oracle; a second H_eff of the same
+    shape takes the cached choice (also from the cache file)."""
+    d = _lib()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("DMRG_TUNE_CACHE", str(cache))
+    p = synth.make_problem(14, 14, 0, 1000, 82)
+    ref = blockops.MiddleHeff(p, "CN").apply(p.psi)
+    ctx, L, R, H, keep = _step(p, arena=8 << 30)
+    T = ctx.heff_create(L, R, 1, d.DMRG_PREC_F32, flags=d.DMRG_HEFF_AUTOTUNE | d.DMRG_HEFF_GRAPH)
+    info = T.info()
+    print(f"[gpu] autotune {info}", flush=True)
+    assert info["tuned"] == "timed" and len(info["candidates"]) >= 3
+    assert all(c["ms_f32"] > 0 for c in info["candidates"])
+    got = _apply(T, p.psi)
+    got32 = _apply(T, p.psi, d.DMRG_PREC_F32)
+    _close(T, H)
+    T2 = ctx.heff_create(L, R, 1, d.DMRG_PREC_F32, flags=d.DMRG_HEFF_AUTOTUNE)
+    info2 = T2.info()
+    _close(T2, L, R, ctx)
+    assert _rel(got, ref) <= 1e-12
+    assert _rel(got32, ref) <= 1e-5
+    assert info2["tuned"] == "cached"
+    assert (info2["balance_target"], info2["tall_min_rows"]) == (info["balance_target"], info["tall_min_rows"])
+    assert cache.read_text().strip()
