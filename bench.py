@@ -135,7 +135,57 @@ def cpu_baseline(F_c5: float):
             "extrapolation": "F_alg ratio (workload / sample) times the sample's product time"}
 
 
+def summarize_profile(d: str):
+    """Per-kernel summary of a rocprofv3 CSV output directory of a --profile-apply
+    run (kernel_stats.csv: calls and durations; counter_collection.csv:
+    per-dispatch counter means over the H_eff product dispatches, i.e. every float
+    chain kernel and the double ones dispatched after the first of them; the
+    copy kernels of the HBM-counter calibration are kept)."""
+    import collections
+    import csv
+    import glob
+    chain = ("slice_kernel", "tall_kernel", "wave_kernel", "reduce_kernel")
+
+    def short(n):
+        n = n.replace("void dmrgk::", "").replace("dmrgk::", "")
+        i = n.find("(")
+        return n[:i] if i > 0 else n
+    out = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*.csv"), recursive=True)):
+        base = os.path.basename(f)
+        if base.endswith("kernel_stats.csv"):
+            out.append(f"# {base}")
+            for r in csv.DictReader(open(f)):
+                name = short(r.get("Name", ""))
+                if any(c in name for c in chain) or "copy" in name.lower():
+                    out.append(f"{name}; calls={r.get('Calls')}; total_ns={r.get('TotalDurationNs')}; "
+                               f"avg_ns={r.get('AverageNs')}; min_ns={r.get('MinNs')}; max_ns={r.get('MaxNs')}")
+        if base.endswith("counter_collection.csv"):
+            rows = list(csv.DictReader(open(f)))
+            first = min((int(r["Dispatch_Id"]) for r in rows
+                         if "<float" in r["Kernel_Name"] and any(c in r["Kernel_Name"] for c in chain)), default=None)
+            agg = collections.defaultdict(lambda: collections.defaultdict(float))
+            disp = collections.defaultdict(set)
+            for r in rows:
+                name = short(r["Kernel_Name"])
+                did = int(r["Dispatch_Id"])
+                keep = any(c in name for c in chain) and first is not None and did >= first
+                if not (keep or "copy" in name.lower()):
+                    continue
+                agg[name][r["Counter_Name"]] += float(r["Counter_Value"])
+                disp[name].add(did)
+            out.append(f"# {base}: per-dispatch means over the product dispatches")
+            for name in sorted(agg):
+                n = len(disp[name])
+                out.append(f"{name}; dispatches={n}; " +
+                           "; ".join(f"{k}={v / n:.6g}" for k, v in sorted(agg[name].items())))
+    print("\n".join(out))
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profile":
+        summarize_profile(sys.argv[2])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10, help="timed Davidson iterations (FP32-mixed policy)")
@@ -146,8 +196,8 @@ def main():
     ap.add_argument("--converge", action="store_true",
                     help="also run both policies to convergence (residual <= 1e-6, at most 300 iterations)")
     ap.add_argument("--profile-apply", type=int, default=0,
-                    help="only build once and run this many FP32 and FP64 products (for profilers); with "
-                         "DMRG_TUNE_CACHE naming the cache a previous run wrote, no tuning products run")
+                    help="only build once and run this many FP32 and FP64 products (for profilers); no "
+                         "tuning products run (set DMRG_BALANCE to the tuned choice of a bench run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU (sub-Hamiltonian) path is not part of this build",
@@ -211,7 +261,9 @@ def main():
     need["heff"] = dmrg.query_workspace(ctx, dmrg.DMRG_WS_HEFF, dmrg.WsHeff(L.ptr, R.ptr, roots, dmrg.DMRG_PREC_F32))
     # products replay a graph of their launches; the work list's parameters are
     # chosen by timing candidates (the autotuner), its choice reported below
-    flags = dmrg.DMRG_HEFF_AUTOTUNE | (0 if args.profile_apply else dmrg.DMRG_HEFF_GRAPH)
+    # under a profiler (--profile-apply) the tuning products stay out of the trace:
+    # the work list takes its defaults, or DMRG_BALANCE (the tuned choice of a bench run)
+    flags = 0 if args.profile_apply else dmrg.DMRG_HEFF_AUTOTUNE | dmrg.DMRG_HEFF_GRAPH
     H = timed("heff_create", lambda: ctx.heff_create(L, R, roots, dmrg.DMRG_PREC_F32, flags=flags))
     ms_build = sum(stages.values())
     dav_kw = dict(max_subspace=max(24, 4 * roots))

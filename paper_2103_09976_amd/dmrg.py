@@ -65,7 +65,7 @@ class HeffInfo(C.Structure):
                 ("tuned", C.c_int32), ("n_candidates", C.c_int32), ("candidate_ms", C.c_float * 8),
                 ("candidate_balance", C.c_int32 * 8), ("candidate_tall_min", C.c_int32 * 8),
                 ("graphs", C.c_int32), ("graph_launches", C.c_int64), ("tasks", C.c_int64),
-                ("reductions", C.c_int32)]
+                ("reductions", C.c_int32), ("partial_elems", C.c_int64)]
 
 
 class WsBlock(C.Structure):
@@ -311,7 +311,7 @@ class Heff:
                 "candidates": [{"balance_target": x.candidate_balance[i], "tall_min_rows": x.candidate_tall_min[i],
                                 "ms_f32": round(float(x.candidate_ms[i]), 3)} for i in range(n)],
                 "graphs": x.graphs, "graph_launches": x.graph_launches, "tasks": x.tasks,
-                "reductions": x.reductions}
+                "reductions": x.reductions, "partial_elems": x.partial_elems}
 
     def psi_layout(self):
         """[(qn_left, s1, s2, qn_right, rows, cols, offset)] of the layout in use."""

@@ -9,7 +9,9 @@ FCI ground energy (lowest eigenvalue of the determinant-space matrix).
 * C4T: 76 orbitals, 113 electrons, S_z = 1/2 at M = 48, eight seeded start
   vectors (the 8-root block), scheme CN with the middle transform;
 * C5T: 108 orbitals, 30 electrons, S_z = 0 at M = 48, sub-Hamiltonian 1 of 16
-  (integrals masked by oracle.share, eq. sub-h / proc-def-nc), scheme NC.
+  (integrals masked by oracle.share, eq. sub-h / proc-def-nc), scheme NC;
+* C2E: the lowest 1 and 8 eigenvalues of the 24-orbital H_eff by ARPACK on the
+  oracle's product (reference energies of the Davidson tests).
 
 Usage: python -m tests.golden.make_golden [NAME ...]   (default: all)
 """
@@ -27,7 +29,7 @@ import synth  # noqa: E402
 from oracle import blockops, fci, share  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ALL = ("C1", "C2", "C4T", "C5T")
+ALL = ("C1", "C2", "C4T", "C5T", "C2E")
 
 
 def twin_vectors(p, name):
@@ -39,7 +41,27 @@ def twin_vectors(p, name):
     return synth.random_vectors(p.psi.size, n, synth.TWINS[name]["seed_base"] + 4)
 
 
+def arpack_energies(name="C2", roots=(1, 8)):
+    """Lowest eigenvalues of the oracle's H_eff (scheme CN) by ARPACK (scipy's
+    eigsh on the oracle's product, tol 1e-12): the reference energies of the
+    1- and 8-root Davidson tests at the 24-orbital workload."""
+    import scipy.sparse.linalg as sla
+    t0 = time.time()
+    p = synth.config_problem(name)
+    H = blockops.MiddleHeff(p, "CN")
+    n = p.psi.size
+    op = sla.LinearOperator((n, n), matvec=H.apply, dtype=float)
+    out = {"source": "scipy.sparse.linalg.eigsh(oracle.blockops.MiddleHeff(scheme=CN), which=SA, tol=1e-12)"}
+    for k in roots:
+        w = sla.eigsh(op, k=k, which="SA", tol=1e-12, v0=p.psi.copy(), ncv=max(2 * k + 1, 24))[0]
+        out[f"energies_{k}"] = [float(x) for x in np.sort(w)]
+    out["seconds"] = round(time.time() - t0, 1)
+    return out
+
+
 def run(name):
+    if name == "C2E":
+        return arpack_energies()
     t0 = time.time()
     p = synth.config_problem(name)
     m = {"dim": int(p.psi.size)}

@@ -538,3 +538,76 @@ def test_autotune_choice_cache_and_parity(monkeypatch, tmp_path):
     assert info2["tuned"] == "cached"
     assert (info2["balance_target"], info2["tall_min_rows"]) == (info["balance_target"], info["tall_min_rows"])
     assert cache.read_text().strip()
+
+
+@pytest.mark.parametrize("name", ["C4T", "C5T"])
+def test_contract_shape_twins(name):
+    """The two largest workloads' shapes at reduced bond dimension, against the
+    oracle's stored products: 76 orbitals, 113 electrons, S_z = 1/2 (CN +
+    middle transform, the 8 seeded vectors of an 8-root block in one call) and
+    108 orbitals, 30 electrons, the sub-Hamiltonian share 1 of 16 (NC-owned
+    operators).  FP64 <= 1e-12 per vector, FP32 <= 1e-5."""
+    import torch
+    d = _lib()
+    p = synth.config_problem(name)
+    gold = np.load(os.path.join(GOLD, f"{name}_sigma.npy"))
+    nroot = synth.TWIN_ROOTS[name]
+    X = p.psi[None, :] if nroot == 1 else synth.random_vectors(p.psi.size, nroot, synth.TWINS[name]["seed_base"] + 4)
+    gold = gold.reshape(nroot, -1)
+    ctx, L, R, H, keep = _step(p, arena=16 << 30, n_roots=nroot)
+    n = H.dim
+    assert n == X.shape[1]
+    x64 = torch.from_numpy(X.ravel().copy()).cuda()
+    y64 = torch.empty_like(x64)
+    H.apply(x64, y64, d.DMRG_PREC_F64, nroot)
+    x32 = x64.float()
+    y32 = torch.empty_like(x32)
+    H.apply(x32, y32, d.DMRG_PREC_F32, nroot)
+    torch.cuda.synchronize()
+    got64 = y64.cpu().numpy().reshape(nroot, n)
+    got32 = y32.double().cpu().numpy().reshape(nroot, n)
+    _close(H, L, R, ctx)
+    for v in range(nroot):
+        e64, e32 = _rel(got64[v], gold[v]), _rel(got32[v], gold[v])
+        print(f"[gpu] {name} vector {v}: f64 {e64:.2e} f32 {e32:.2e}", flush=True)
+        assert e64 <= 1e-12
+        assert e32 <= 1e-5
+
+
+def test_c2_davidson_vs_arpack_one_and_eight_roots():
+    """The 24-orbital workload: Davidson energies for 1 and 8 roots (FP64 and the
+    FP32-mixed policy) against ARPACK on the oracle's product (stored), 1e-10."""
+    import torch
+    d = _lib()
+    ref = json.load(open(os.path.join(GOLD, "golden.json")))["C2E"]
+    p = synth.config_problem("C2")
+    for k in (1, 8):
+        ctx, L, R, H, keep = _step(p, arena=8 << 30, n_roots=k)
+        start = p.psi.copy() if k == 1 else synth.random_vectors(H.dim, k, 2005).ravel().copy()
+        for prec in (d.DMRG_PREC_F64, d.DMRG_PREC_F32):
+            psi = torch.from_numpy(start.copy()).cuda()
+            print(f"[gpu] C2 davidson roots={k} precision={prec}", flush=True)
+            e, st = H.davidson(psi, k, tol=1e-7, precision=prec, max_subspace=max(24, 4 * k), max_iter=600)
+            assert st["converged"] == 1, st
+            err = np.abs(np.sort(e) - np.array(ref[f"energies_{k}"])).max()
+            print(f"[gpu] roots={k} prec={prec} |E - E_arpack| = {err:.2e} iters={st['iters']}", flush=True)
+            assert err <= 1e-10
+        _close(H, L, R, ctx)
+
+
+def test_sixteen_shares_sum_to_full_product():
+    """Sum of sub-Hamiltonians on the GPU (Section II.B, eq. sum-h): the 16
+    shares' products (each its own NC build with the owned pairs only) add up
+    to the full H_eff psi, 1e-12 (12 orbitals)."""
+    import torch
+    p = synth.make_problem(12, 12, 0, 60, 28)
+    ctx, L, R, H, keep = _step(p, "NC")
+    full = _apply(H, p.psi)
+    _close(H, L, R, ctx)
+    acc = np.zeros_like(full)
+    for pid in range(1, 17):
+        q = synth.make_problem(12, 12, 0, 60, 28, n_proc=16, proc_id=pid)
+        ctx, L, R, H, keep = _step(q, "NC")
+        acc += _apply(H, q.psi)
+        _close(H, L, R, ctx)
+    assert _rel(acc, full) <= 1e-12
