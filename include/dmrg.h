@@ -215,6 +215,7 @@ typedef struct {
     int64_t graph_launches;       /* products run as graph replays */
     int64_t tasks;                /* output tiles of the work list */
     int32_t reductions;           /* split tiles summed by the reduction */
+    int64_t partial_elems;        /* elements of their partial tiles, per vector */
 } dmrg_heff_info;
 dmrg_status dmrg_heff_get_info(const dmrg_heff* H, dmrg_heff_info* info);
 /* Readback of the layout in use (host arrays of capacity >= n, any may be
@@ -229,6 +230,19 @@ int32_t dmrg_heff_psi_layout(const dmrg_heff* H, int32_t n, int32_t* qn_left, in
  * for FP64 only).  Vectors run in batches of n_roots. */
 dmrg_status dmrg_heff_apply(dmrg_heff* H, int32_t precision, int32_t n_vec,
                             const void* psi, void* sigma, void* stream);
+
+/* Allocation-free product, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): dmrg_heff_apply with the partial tiles of split tasks in the
+ * library's static device array (256 MiB on each GPU the library runs on,
+ * held until the process ends) instead of the context arena, always launched
+ * eagerly.  It allocates nothing and calls no allocating routine.  Fails with
+ * DMRG_E_WORKSPACE, before any device work, when one vector's partial tiles
+ * exceed the array; vectors go in batches of as many as it holds.  Every call
+ * on one GPU shares the array (nothing in it must start at zero): calls that
+ * overlap on one GPU race.  Arguments and results as dmrg_heff_apply. */
+dmrg_status dmrg_heff_apply_static(dmrg_heff* H, int32_t precision, int32_t n_vec, const void* psi, void* sigma,
+                                   void* stream);
 
 /* diag[dim] (device, double) = diagonal of H_eff (Davidson preconditioner). */
 dmrg_status dmrg_heff_diag(dmrg_heff* H, double* diag, void* stream);

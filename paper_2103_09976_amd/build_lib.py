@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdmrg_hip.so")
-SOURCES = ["kernels.hip", "core.cpp", "build.cpp", "heff.cpp", "davidson.cpp"]
+SOURCES = ["kernels.hip", "core.cpp", "build.cpp", "heff.cpp", "davidson.cpp", "static_scratch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

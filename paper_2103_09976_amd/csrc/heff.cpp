@@ -1142,6 +1142,8 @@ int32_t dmrg_heff_terms(const dmrg_heff* H, int32_t* n2, int32_t* n1, int32_t* n
 // go in batches of as many as the partial buffer holds (n_roots for H's own).
 dmrg_status heff_apply_impl(dmrg_heff* H, int32_t precision, int32_t n_vec, const void* psi, void* sigma,
                             void* partial, int64_t partial_bytes, void* stream) {
+    // the static-scratch variant never instantiates a graph (that may allocate)
+    const bool graph = (H ? (H->flags & DMRG_HEFF_GRAPH) : 0) && !partial;
     if (!H || !psi || !sigma) return fail(DMRG_E_ARG, "null argument");
     if (n_vec < 1 || n_vec > 65535) return fail(DMRG_E_ARG, "bad n_vec");
     if (psi == sigma) return fail(DMRG_E_ARG, "psi and sigma must not alias");
@@ -1166,8 +1168,7 @@ dmrg_status heff_apply_impl(dmrg_heff* H, int32_t precision, int32_t n_vec, cons
             b.p[2] = (double*)psi + (int64_t)v0 * H->dim;
             b.p[3] = (double*)sigma + (int64_t)v0 * H->dim;
             b.vstride[2] = b.vstride[3] = H->dim;
-            st = (H->flags & DMRG_HEFF_GRAPH) ? run_graph<double>(H, precision, b, nv, stream)
-                                              : run_work_f64(H->work, b, nv, stream);
+            st = graph ? run_graph<double>(H, precision, b, nv, stream) : run_work_f64(H->work, b, nv, stream);
         } else {
             if (H->f32_region < 0) return fail(DMRG_E_STATE, "H_eff was created for FP64 products only");
             dmrgk::Bases<float> b = bases32(H);
@@ -1175,8 +1176,7 @@ dmrg_status heff_apply_impl(dmrg_heff* H, int32_t precision, int32_t n_vec, cons
             b.p[2] = (float*)psi + (int64_t)v0 * H->dim;
             b.p[3] = (float*)sigma + (int64_t)v0 * H->dim;
             b.vstride[2] = b.vstride[3] = H->dim;
-            st = (H->flags & DMRG_HEFF_GRAPH) ? run_graph<float>(H, precision, b, nv, stream)
-                                              : run_work_f32(H->work, b, nv, stream);
+            st = graph ? run_graph<float>(H, precision, b, nv, stream) : run_work_f32(H->work, b, nv, stream);
         }
         if (st != DMRG_OK) return st;
     }
@@ -1269,6 +1269,7 @@ dmrg_status dmrg_heff_get_info(const dmrg_heff* H, dmrg_heff_info* info) {
     for (int c = 0; c < dmrgk::kNumClass; ++c) nt += H->work.ntask[c];
     x.tasks = nt;
     x.reductions = H->work.nred;
+    x.partial_elems = H->part_elems;
     *info = x;
     return DMRG_OK;
 }
