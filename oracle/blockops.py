@@ -680,24 +680,23 @@ def build_right(prob, ints: Integrals, nsites: int, scheme: str) -> Block:
     return Y
 
 
-class MiddleHeff:
-    """H_eff of the middle step as an explicit term list over L' x R'."""
+class TwoSiteHeff:
+    """H_eff of a two-site step as an explicit term list over L' x R'.
 
-    def __init__(self, prob, scheme: str = "CN", h1e=None, g2e=None):
-        self.prob = prob
-        h = prob.h1e if h1e is None else h1e
-        g = prob.g2e if g2e is None else g2e
-        ints = Integrals(h, g)
+    Lb: normal left block of sites [0, KL); Rb: complementary right block of
+    sites [KL + 2, K); the dots are d1 = KL and d2 = KL + 1 (Appendix A,
+    effective eigenproblem, with the NC partition of Appendix B).
+    """
+
+    def __init__(self, Lb: Block, Rb: Block, ints: Integrals, KL: int, K: int, target: Q,
+                 e_core: float = 0.0):
         self.ints = ints
-        K, KL = prob.K, prob.KL
+        self.K, self.KL, self.target = K, KL, target
         d1, d2 = KL, KL + 1
-        Lb = build_left(prob, ints, KL)
-        Rb = build_right(prob, ints, prob.KR, scheme)
         lp_orbs = list(range(0, 2 * (KL + 1)))
         rp_orbs = list(range(2 * (KL + 1), 2 * K))
-        if scheme == "CN":
-            Rb = to_complementary(Rb, ints, list(range(0, 2 * (KL + 2))))
         self.Lb, self.Rb = Lb, Rb
+        self.lb_dims, self.rb_dims = dict(Lb.basis), dict(Rb.basis)
         self.enl_L, Lp = grow_left(Lb, Site(d1, ints), ints, rp_orbs)
         self.enl_R, Rp = grow_right_compl(Rb, Site(d2, ints), ints, lp_orbs)
         self.Lp, self.Rp = Lp, Rp
@@ -717,12 +716,12 @@ class MiddleHeff:
             for q in lp_orbs:
                 terms.append((1.0, Lp.B(p, q), Rp.ops[("Q", p, q)]))
         self.terms = terms
-        self.e_core = prob.e_core
+        self.e_core = e_core
         self._layout()
 
     def _layout(self):
-        lb, rb = self.prob.lb_dims, self.prob.rb_dims
-        tgt = self.prob.target
+        lb, rb = self.lb_dims, self.rb_dims
+        tgt = self.target
         self.blocks = []
         off = 0
         loff = {}
@@ -776,6 +775,24 @@ class MiddleHeff:
         if self.e_core:
             out = out + self.e_core * psi
         return out
+
+
+class MiddleHeff(TwoSiteHeff):
+    """H_eff of the middle step of a problem (dots K/2 - 1, K/2), with the
+    right block built in the NC scheme or in the CN scheme and then turned
+    complementary (Section III.A)."""
+
+    def __init__(self, prob, scheme: str = "CN", h1e=None, g2e=None):
+        self.prob = prob
+        h = prob.h1e if h1e is None else h1e
+        g = prob.g2e if g2e is None else g2e
+        ints = Integrals(h, g)
+        K, KL = prob.K, prob.KL
+        Lb = build_left(prob, ints, KL)
+        Rb = build_right(prob, ints, prob.KR, scheme)
+        if scheme == "CN":
+            Rb = to_complementary(Rb, ints, list(range(0, 2 * (KL + 2))))
+        super().__init__(Lb, Rb, ints, KL, K, prob.target, prob.e_core)
 
     def renormalize_left(self) -> Block:
         """Post-solve renormalization of the L' operators into the next basis."""

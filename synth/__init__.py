@@ -316,3 +316,74 @@ def random_vectors(dim: int, n: int, seed: int) -> np.ndarray:
     v = rng.standard_normal((n, dim))
     v /= np.linalg.norm(v, axis=1, keepdims=True)
     return v
+
+
+# ---------------------------------------------------------------------------
+# two-site sweeps
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SweepInputs:
+    """Inputs of a run of two-site sweeps over sites 0..K-1.
+
+    The starting MPS is the left block of site 0 (left_iso0, its sector
+    dimensions left_dims1) and right blocks of n = 1..K-3 sites built through
+    random isometries (right_iso[n-1] adds site K-n to the block of n-1
+    sites; right_dims[n] are the dimensions of the block of n sites).
+    """
+    name: str
+    K: int
+    target: Q
+    M: Optional[int]
+    h1e: np.ndarray
+    g2e: np.ndarray
+    e_core: float
+    left_dims1: Dict[Q, int]
+    left_iso0: Dict[Q, np.ndarray]
+    right_dims: List[Dict[Q, int]]
+    right_iso: List[Dict[Q, np.ndarray]]
+    seed_base: int
+
+
+def make_sweep_inputs(K: int, n_elec: int, two_sz: int, M: Optional[int], seed_base: int,
+                      name: str = "") -> SweepInputs:
+    """Seeds: integrals seed_base+1 (as make_problem), isometries seed_base+2."""
+    assert K >= 4
+    Na = (n_elec + two_sz) // 2
+    Nb = (n_elec - two_sz) // 2
+    assert Na + Nb == n_elec and Na - Nb == two_sz
+    target = (Na, Nb)
+    h, g = make_integrals(K, seed_base + 1)
+    rng = np.random.default_rng(seed_base + 2)
+
+    def iso_for(old: Dict[Q, int], new: Dict[Q, int]) -> Dict[Q, np.ndarray]:
+        out = {}
+        for q, m in new.items():
+            d = sum(dd for (_, _, dd) in enlarged_segments(old, q))
+            out[q] = random_isometry(rng, d, m)
+        return out
+
+    vac = {(0, 0): 1}
+    l1 = allocate_dims(K, target, 1, vac, M)
+    liso = iso_for(vac, l1)
+    rdims = [vac]
+    riso = []
+    for n in range(1, K - 2):
+        new = allocate_dims(K, target, n, rdims[-1], M)
+        riso.append(iso_for(rdims[-1], new))
+        rdims.append(new)
+    return SweepInputs(name=name, K=K, target=target, M=M, h1e=h, g2e=g, e_core=0.0,
+                       left_dims1=l1, left_iso0=liso, right_dims=rdims, right_iso=riso,
+                       seed_base=seed_base)
+
+
+def sweep_seed(inp: SweepInputs, sweep: int, backward: bool, KL: int) -> int:
+    """Seed of the Davidson start vector at one step of a sweep."""
+    return inp.seed_base + 10 + 1000 * sweep + 2 * KL + (1 if backward else 0)
+
+
+def unit_vector(dim: int, seed: int, n: int = 1) -> np.ndarray:
+    """n seeded Gaussian vectors of length dim, each of unit norm ([n, dim])."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, dim))
+    return x / np.linalg.norm(x, axis=1, keepdims=True)
