@@ -540,7 +540,7 @@ def test_autotune_choice_cache_and_parity(monkeypatch, tmp_path):
     assert cache.read_text().strip()
 
 
-@pytest.mark.parametrize("name", ["C4T"])
+@pytest.mark.parametrize("name", ["C4T", "C5T"])
 def test_contract_shape_twins(name):
     """The two largest workloads' shapes at reduced bond dimension, against the
     oracle's stored products: 76 orbitals, 113 electrons, S_z = 1/2 (CN +
@@ -590,3 +590,31 @@ def test_sixteen_shares_sum_to_full_product():
         acc += _apply(H, q.psi)
         _close(H, L, R, ctx)
     assert _rel(acc, full) <= 1e-12
+
+
+def test_c2_davidson_vs_arpack_one_and_eight_roots():
+    """The 24-orbital workload: Davidson energies for 1 and 8 roots (FP64 and the
+    FP32-mixed policy) against ARPACK on the oracle's product (stored), 1e-10."""
+    import torch
+    d = _lib()
+    ref = json.load(open(os.path.join(GOLD, "golden.json")))["C2E"]
+    p = synth.config_problem("C2")
+    for k in (1, 8):
+        ctx, L, R, H, keep = _step(p, arena=8 << 30, n_roots=k)
+        # root j starts on the basis state of the j-th lowest diagonal element plus a
+        # seeded vector at 1/10 weight (a random block alone can settle on excited roots)
+        dg = torch.empty(H.dim, dtype=torch.float64, device="cuda:0")
+        H.diag(dg)
+        idx = torch.topk(dg, k, largest=False).indices.cpu().numpy()
+        start = 0.1 * synth.random_vectors(H.dim, k, 2005).reshape(k, H.dim)
+        start[np.arange(k), idx] += 1.0
+        start = start.ravel().copy()
+        for prec in (d.DMRG_PREC_F64, d.DMRG_PREC_F32):
+            psi = torch.from_numpy(start.copy()).cuda()
+            print(f"[gpu] C2 davidson roots={k} precision={prec}", flush=True)
+            e, st = H.davidson(psi, k, tol=1e-7, precision=prec, max_subspace=max(24, 4 * k), max_iter=600)
+            assert st["converged"] == 1, st
+            err = np.abs(np.sort(e) - np.array(ref[f"energies_{k}"])).max()
+            print(f"[gpu] roots={k} prec={prec} |E - E_arpack| = {err:.2e} iters={st['iters']}", flush=True)
+            assert err <= 1e-10
+        _close(H, L, R, ctx)
