@@ -353,6 +353,14 @@ def main():
     # ---- a6: renormalization of the blocked left operators into the next basis
     N = timed("renormalize_left", lambda: H.renormalize(ni))
     N.free()
+    # ---- decimation of the roots reached above (state-averaged density matrix,
+    # truncation to M) and the transformation into the decimated basis
+    note("decimation")
+    iso = timed("decimate", lambda: H.decimate(out_psi, dmrg.DMRG_LEFT, prob.M or 0, n_vec=roots))
+    N = timed("renormalize_decimated", lambda: H.renormalize(iso))
+    decim = dict(iso.info, ms=stages["decimate"], ms_renormalize=stages["renormalize_decimated"])
+    N.free()
+    iso.free()
 
     t32m, t64m = float(np.median(t32)), float(np.median(t64))
     Ft = F * roots
@@ -390,6 +398,7 @@ def main():
         f"dE_mixed_vs_f64_after_{W['iters']}_iterations": float(np.max(np.abs(np.sort(em) - np.sort(ed)))),
         "residual_after_fixed_iterations": {"mixed": sm["max_residual"], "f64": sd["max_residual"]},
         "converged": conv,
+        "decimation": decim,
         "ms_build": round(ms_build, 1),
         "build_stages_ms": stages,
         "arena_needed_bytes": need,

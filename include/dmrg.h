@@ -21,6 +21,8 @@
  *   dmrg_heff_apply     -> H_eff psi (Appendix A, effective eigenproblem)
  *   dmrg_davidson       -> Davidson solution of the effective eigenproblem
  *                          (also one iteration at a time: dmrg_davidson_step)
+ *   dmrg_decimate       -> decimation: the new renormalized basis from the
+ *                          reduced density matrix of the solution (Appendix A)
  *   dmrg_heff_renormalize, dmrg_renormalize
  *                       -> transformation of blocked operators into a new
  *                          renormalized basis (Appendix A)
@@ -30,7 +32,8 @@
  *   spin-orbital p = 2*i + s (s = 0 alpha, 1 beta), spatial i = 0..K-1;
  *   sector label (n_alpha, n_beta); site basis |0>,|a>,|b>,|ab>;
  *   left block Lb = sites [0, KL), dots d1 = KL, d2 = KL+1, right block
- *   Rb = [KL+2, K), KL = K/2 - 1 (K even);
+ *   Rb = [KL+2, K) (the middle step: KL = K/2 - 1; a sweep moves KL from 1
+ *   to K-3 and back);
  *   a block grown by one site orders the rows of each enlarged sector by site
  *   state (0, a, b, ab), each segment holding the old block's sector
  *   q - q_site in the old block's order (sectors sorted by (n_alpha, n_beta));
@@ -290,6 +293,50 @@ dmrg_status dmrg_heff_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_o
  * isometry's rows do not match the enlarged sectors. */
 dmrg_status dmrg_renormalize(dmrg_ctx* ctx, const dmrg_opset* in, const dmrg_bsm* isometry, dmrg_opset** out,
                              void* stream);
+
+/* Decimation (Appendix A, after the effective eigenproblem): the new
+ * renormalized basis of the block that moves on, from the reduced density
+ * matrix of the two-site wavefunction.  side DMRG_LEFT: sectors of the
+ * enlarged left block L' = Lb + d1 (rows in the enlarged order above; pass
+ * the result to dmrg_heff_renormalize or dmrg_renormalize of Lb);
+ * DMRG_RIGHT: sectors of R' = d2 + Rb (for dmrg_renormalize of Rb).
+ *   psi[n_vec * dim] (device, double): the roots, in H's layout; the density
+ *     matrix averages them with equal weights, rho_L = sum_k Psi_k Psi_k^T /
+ *     n_vec per sector (rho_R: Psi_k^T Psi_k), Psi_k the wavefunction as a
+ *     matrix over (L' state, R' state);
+ *   noise, xi: noise >= 0; when noise > 0 the density matrix gains
+ *     noise * sum_k Xi_k Xi_k^T / n_vec (Xi_k^T Xi_k on the right), Xi_k the
+ *     caller's perturbations (xi[n_vec * dim], device, in H's layout; ignored
+ *     when noise == 0): positive semidefinite, independent of the roots' signs;
+ *   max_states: M, the states to keep (<= 0: no limit).  Kept are the M
+ *     largest weights over all sectors, plus every state within 1e-8 w_max
+ *     of the M-th (no multiplet of the spin symmetry is cut), minus every
+ *     state of weight <= 1e-14 w_max (w_max the largest weight).
+ * The density matrices are GEMMs on the library's FP64 MFMA kernels; each
+ * sector's is diagonalised with rocSOLVER (dsyevd), its workspace taken from
+ * the arena.  *out: the isometry, columns by descending weight within each
+ * sector, sectors without kept states omitted; it lives in the arena until
+ * dmrg_iso_free.  info (optional): kept states, sectors, truncation error
+ * (discarded / total weight) and total weight.  Synchronizes `stream`.
+ * DMRG_E_ARG for bad arguments or a zero wavefunction, DMRG_E_WORKSPACE when
+ * the arena cannot hold Psi, the density matrices and the solver workspace,
+ * DMRG_E_NONFINITE for a non-finite weight. */
+typedef struct dmrg_iso dmrg_iso;
+typedef struct {
+    int64_t kept;             /* states kept (the new bond dimension) */
+    int32_t n_blocks;         /* sectors of the new basis */
+    double trunc_err;         /* discarded weight / total weight */
+    double weight_total;      /* trace of the density matrix */
+} dmrg_decim_info;
+dmrg_status dmrg_decimate(dmrg_heff* H, int32_t side, int32_t n_vec, const double* psi, double noise,
+                          const double* xi, int32_t max_states, dmrg_iso** out, dmrg_decim_info* info,
+                          void* stream);
+/* The isometry as a dmrg_bsm (pointers owned by iso, valid until it is freed). */
+dmrg_status dmrg_iso_bsm(const dmrg_iso* iso, dmrg_bsm* view);
+/* Kept weights (host), block by block in the order of the bsm view,
+ * descending within a block; copies min(n, count) and returns the count. */
+int64_t dmrg_iso_weights(const dmrg_iso* iso, int64_t n, double* w);
+void dmrg_iso_free(dmrg_iso* iso);
 
 /* Arena bytes a call needs (free, beyond what is in use), computed on the
  * host without device work.  what / args:

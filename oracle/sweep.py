@@ -14,8 +14,9 @@ Readings fixed here (the paper does not spell them out):
 
 * density matrix of the left side rho_L = sum over roots of Psi Psi^T / n,
   of the right side rho_R = sum Psi^T Psi / n (equal weights for several
-  roots); with noise, Psi is replaced by Psi + noise * Xi for a given
-  perturbation Xi before the density matrix is formed;
+  roots); noise adds noise * Xi Xi^T / n per root (Xi^T Xi on the right) for
+  a given perturbation Xi: a positive semidefinite term that does not depend
+  on the sign of a root;
 * kept states: the M largest weights over all sectors, plus every further
   state whose weight lies within tie_rel * w_max of the M-th (so no
   multiplet of the spin symmetry is cut, also when a solver's residual
@@ -51,14 +52,17 @@ class Decimation:
     kept: int = 0
 
 
-def density_matrices(H: TwoSiteHeff, psis: List[np.ndarray], side: str) -> Dict[Q, np.ndarray]:
+def density_matrices(H: TwoSiteHeff, psis: List[np.ndarray], side: str, noise: float = 0.0,
+                     xis: Optional[List[np.ndarray]] = None) -> Dict[Q, np.ndarray]:
     """Reduced density matrix of the enlarged left (side 'left') or right
-    ('right') block, per sector, averaged over the given wavefunctions."""
+    ('right') block, per sector, averaged over the given wavefunctions, plus
+    noise times the same form of the perturbations."""
     rho: Dict[Q, np.ndarray] = {}
-    for psi in psis:
+    terms = [(1.0, p) for p in psis] + ([(noise, x) for x in xis] if noise else [])
+    for c, psi in terms:
         for (QL, QR), X in H.to_matrix(psi).items():
             q, R = (QL, X @ X.T) if side == "left" else (QR, X.T @ X)
-            rho[q] = rho[q] + R if q in rho else R
+            rho[q] = rho[q] + c * R if q in rho else c * R
     return {q: r / len(psis) for q, r in sorted(rho.items())}
 
 
@@ -103,9 +107,7 @@ def decimate(H: TwoSiteHeff, psis: List[np.ndarray], side: str, M: Optional[int]
              xis: Optional[List[np.ndarray]] = None, tie_rel: float = TIE_REL) -> Decimation:
     """Decimation of one step (Appendix A): the new basis of the side that
     moves on, from the density matrix of the (optionally perturbed) roots."""
-    if noise:
-        psis = [p + noise * x for p, x in zip(psis, xis)]
-    return select_states(density_matrices(H, psis, side), M, tie_rel)
+    return select_states(density_matrices(H, psis, side, noise, xis), M, tie_rel)
 
 
 def lowest_roots(H: TwoSiteHeff, v0: np.ndarray, n_roots: int = 1, dense_max: int = 200):

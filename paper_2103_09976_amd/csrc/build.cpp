@@ -772,7 +772,11 @@ dmrg_status dmrg_create(dmrg_ctx** out, int32_t device, void* arena, int64_t are
     return DMRG_OK;
 }
 
-void dmrg_destroy(dmrg_ctx* ctx) { delete ctx; }
+void dmrg_destroy(dmrg_ctx* ctx) {
+    if (!ctx) return;
+    release_solver(ctx);
+    delete ctx;
+}
 
 int64_t dmrg_arena_used(const dmrg_ctx* ctx) { return ctx ? ctx->arena.used : 0; }
 int64_t dmrg_arena_peak(const dmrg_ctx* ctx) { return ctx ? ctx->arena.peak : 0; }
@@ -808,7 +812,7 @@ static void apply_share_mask(Ctx* ctx) {
 dmrg_status dmrg_set_integrals(dmrg_ctx* ctx, int32_t K, int32_t n_elec, int32_t two_sz, const double* h1e,
                                const double* g2e, double e_core, int32_t n_proc, int32_t proc_id) {
     if (!ctx || !h1e || !g2e) return fail(DMRG_E_ARG, "null argument");
-    if (K < 4 || K % 2 || K > 512) return fail(DMRG_E_ARG, "K must be even, 4 <= K <= 512");
+    if (K < 4 || K > 512) return fail(DMRG_E_ARG, "K must satisfy 4 <= K <= 512");
     if ((n_elec + two_sz) % 2 || n_elec < 0 || std::abs(two_sz) > n_elec || n_elec > 2 * K)
         return fail(DMRG_E_ARG, "inconsistent n_elec / two_sz");
     if (n_proc < 1 || proc_id < 1 || proc_id > n_proc) return fail(DMRG_E_ARG, "bad n_proc / proc_id");
@@ -1045,7 +1049,7 @@ dmrg_status dmrg_query_workspace(const dmrg_ctx* cctx, int32_t what, const void*
         ctx = &local;
         if (what == DMRG_WS_BLOCK) {
             const dmrg_ws_block* a = (const dmrg_ws_block*)args;
-            if (a->K < 4 || a->K % 2 || a->K > 512) return fail(DMRG_E_ARG, "K must be even, 4 <= K <= 512");
+            if (a->K < 4 || a->K > 512) return fail(DMRG_E_ARG, "K must satisfy 4 <= K <= 512");
             if ((a->n_elec + a->two_sz) % 2 || a->n_elec < 0 || std::abs(a->two_sz) > a->n_elec)
                 return fail(DMRG_E_ARG, "inconsistent n_elec / two_sz");
             if (a->n_proc < 1 || a->proc_id < 1 || a->proc_id > a->n_proc)

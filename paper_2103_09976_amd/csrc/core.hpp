@@ -172,6 +172,9 @@ struct Ctx {
     // as in a real call, but no device work is issued and no device memory is
     // touched; the arena's high-water mark then gives the size the call needs.
     bool dry = false;
+    // rocBLAS handle of the decimation's eigensolver (created on first use,
+    // released by dmrg_destroy)
+    void* solver = nullptr;
     bool has_ints = false;
     int K = 0, na = 0, nb = 0;
     double e_core = 0.0;
@@ -340,6 +343,13 @@ dmrg_status renormalize_grown(Ctx* C, const OpSetImpl& old, const OpSetImpl* tem
 
 struct dmrg_heff;
 dmrg::Ctx* heff_ctx(const dmrg_heff* H);
+namespace dmrg {
+// wavefunction sub-block (a, s1, s2, b) of an H_eff: a, b index the sectors
+// of its left / right block; m_a x m_b row-major at element `off`
+struct PsiSub { int a, s1, s2, b, ma, mb; int64_t off; };
+void heff_psi_subblocks(const dmrg_heff* H, const OpSetImpl*& Lb, const OpSetImpl*& Rb, std::vector<PsiSub>& out);
+void release_solver(Ctx* C);
+}  // namespace dmrg
 
 struct dmrg_ctx : dmrg::Ctx {};
 struct dmrg_opset : dmrg::OpSetImpl {

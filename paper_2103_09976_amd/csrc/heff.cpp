@@ -394,7 +394,7 @@ static dmrg_status apply_layout(dmrg_heff* H, const Basis& lb) {
 
 static dmrg_status build_heff(dmrg_heff* H, void* stream) {
     Ctx* C = H->ctx;
-    const int K = C->K, KL = K / 2 - 1;
+    const int K = C->K, KL = H->Lb->nsites;   // dots d1 = KL, d2 = KL + 1
     const OpSetImpl& Lb = *H->Lb;
     const OpSetImpl& Rb = *H->Rb;
     std::vector<int> lp, rp;
@@ -1049,16 +1049,23 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
 
 Ctx* heff_ctx(const dmrg_heff* H) { return H->ctx; }
 
+void dmrg::heff_psi_subblocks(const dmrg_heff* H, const OpSetImpl*& Lb, const OpSetImpl*& Rb, std::vector<PsiSub>& out) {
+    Lb = H->Lb;
+    Rb = H->Rb;
+    out.clear();
+    for (const PsiBlock& B : H->blocks) out.push_back(PsiSub{B.a, B.s1, B.s2, B.b, B.ma, B.mb, B.off});
+}
+
 extern "C" {
 
 static dmrg_status check_heff_args(const dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_opset* right,
                                    int32_t n_roots, int32_t precision) {
     if (!ctx->has_ints) return fail(DMRG_E_STATE, "integrals not set");
-    const int K = ctx->K, KL = K / 2 - 1;
-    if (left->side != DMRG_LEFT || left->kind != 0 || left->nsites != KL)
-        return fail(DMRG_E_ARG, "left must be the normal left block of K/2-1 sites");
-    if (right->side != DMRG_RIGHT || right->kind != 1 || right->nsites != K - KL - 2)
-        return fail(DMRG_E_ARG, "right must be a complementary right block of K/2-1 sites");
+    const int K = ctx->K, KL = left->nsites;
+    if (left->side != DMRG_LEFT || left->kind != 0 || KL < 1)
+        return fail(DMRG_E_ARG, "left must be a normal left block of at least one site");
+    if (right->side != DMRG_RIGHT || right->kind != 1 || right->nsites < 1 || right->nsites != K - KL - 2)
+        return fail(DMRG_E_ARG, "right must be a complementary right block of the K - 2 - KL sites after the dots");
     if (n_roots < 1 || n_roots > 32) return fail(DMRG_E_ARG, "n_roots must be 1..32");
     if (precision != DMRG_PREC_F64 && precision != DMRG_PREC_F32) return fail(DMRG_E_ARG, "bad precision");
     return DMRG_OK;
@@ -1241,7 +1248,7 @@ dmrg_status dmrg_heff_renormalize(dmrg_heff* H, const dmrg_bsm* isometry, dmrg_o
         return st;
     }
     o->orbs = H->Lb->orbs;
-    const int d1 = H->ctx->K / 2 - 1;
+    const int d1 = H->Lb->nsites;
     o->orbs.push_back(2 * d1);
     o->orbs.push_back(2 * d1 + 1);
     o->nsites = H->Lb->nsites + 1;

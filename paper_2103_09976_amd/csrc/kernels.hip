@@ -1312,4 +1312,41 @@ int launch_nonfinite(const double* x, int64_t n, int* flag, void* stream) {
     return (int)hipGetLastError();
 }
 
+__global__ void psi_gather_kernel(const GatherBlock* __restrict__ blocks, const double* __restrict__ psi,
+                                  int part, int64_t dim, double scale, double* __restrict__ out) {
+    const GatherBlock B = blocks[blockIdx.x];
+    const int64_t v = blockIdx.y;
+    const double* src = psi + v * dim + B.src;
+    double* dst = out + B.dst + part * B.pcol + v * B.vcol;
+    const int64_t n = (int64_t)B.ma * B.mb;
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+        const int64_t i = e / B.mb, j = e - i * B.mb;
+        dst[B.trans ? j * B.ld + i : i * B.ld + j] = scale * src[e];
+    }
+}
+
+int launch_psi_gather(const GatherBlock* blocks, int nblock, int nvec, const double* psi, int part, int64_t dim,
+                      double scale, double* out, void* stream) {
+    if (nblock <= 0 || nvec <= 0) return 0;
+    hipLaunchKernelGGL(psi_gather_kernel, dim3(nblock, nvec), dim3(256), 0, (hipStream_t)stream, blocks, psi, part,
+                       dim, scale, out);
+    return (int)hipGetLastError();
+}
+
+__global__ void evec_gather_kernel(const EvecBlock* __restrict__ blocks, const double* __restrict__ evec,
+                                   double* __restrict__ iso) {
+    const EvecBlock B = blocks[blockIdx.x];
+    const int64_t n = (int64_t)B.d * B.k;
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+        const int64_t i = e / B.k, c = e - i * B.k;
+        iso[B.dst + e] = evec[B.src + i + (B.d - 1 - c) * (int64_t)B.d];
+    }
+}
+
+int launch_evec_gather(const EvecBlock* blocks, int nblock, const double* evec, double* iso, void* stream) {
+    if (nblock <= 0) return 0;
+    hipLaunchKernelGGL(evec_gather_kernel, dim3(nblock), dim3(256), 0, (hipStream_t)stream, blocks, evec, iso);
+    return (int)hipGetLastError();
+}
+
 }  // namespace dmrgk

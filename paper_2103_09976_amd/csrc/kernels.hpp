@@ -193,4 +193,19 @@ int launch_jacobi(const double* A, int n, double* w, double* Z, void* stream);
 // count of non-finite entries -> *flag (int)
 int launch_nonfinite(const double* x, int64_t n, int* flag, void* stream);
 
+// Decimation.  Gather of wavefunction sub-blocks into the dense per-sector
+// matrices Psi_q (side-major): for vector v, element (i, j) of sub-block b
+//   out[b.dst + part * b.pcol + v * b.vcol + (b.trans ? j * b.ld + i : i * b.ld + j)]
+//     = scale * psi[v * dim + b.src + i * b.mb + j]
+// (part 1 places a second set of vectors, the perturbation, after the first).
+// Grid: one workgroup per (sub-block, vector).
+struct GatherBlock { int64_t src, dst, vcol, pcol; int32_t ma, mb, ld, trans; };
+int launch_psi_gather(const GatherBlock* blocks, int nblock, int nvec, const double* psi, int part, int64_t dim,
+                      double scale, double* out, void* stream);
+// kept eigenvectors, descending weight: iso[b.dst + i * b.k + c] =
+// evec[b.src + i + (b.d - 1 - c) * b.d] (column-major ascending eigenvectors
+// of a d x d matrix -> row-major d x k isometry)
+struct EvecBlock { int64_t src, dst; int32_t d, k; };
+int launch_evec_gather(const EvecBlock* blocks, int nblock, const double* evec, double* iso, void* stream);
+
 }  // namespace dmrgk

@@ -68,6 +68,11 @@ class HeffInfo(C.Structure):
                 ("reductions", C.c_int32), ("partial_elems", C.c_int64)]
 
 
+class DecimInfo(C.Structure):
+    _fields_ = [("kept", C.c_int64), ("n_blocks", C.c_int32), ("trunc_err", C.c_double),
+                ("weight_total", C.c_double)]
+
+
 class WsBlock(C.Structure):
     _fields_ = [("K", C.c_int32), ("n_elec", C.c_int32), ("two_sz", C.c_int32), ("n_proc", C.c_int32),
                 ("proc_id", C.c_int32), ("side", C.c_int32), ("n_sites", C.c_int32), ("scheme", C.c_int32),
@@ -136,6 +141,11 @@ _SIGS = {
     "dmrg_opset_basis": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "dmrg_opset_block": (C.c_int32, [C.c_void_p, C.c_char, C.c_int32, C.c_int32, C.c_void_p,
                                      C.c_void_p, C.c_int64]),
+    "dmrg_decimate": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_double, C.c_void_p,
+                                  C.c_int32, C.POINTER(C.c_void_p), C.POINTER(DecimInfo), C.c_void_p]),
+    "dmrg_iso_bsm": (C.c_int32, [C.c_void_p, C.POINTER(Bsm)]),
+    "dmrg_iso_weights": (C.c_int64, [C.c_void_p, C.c_int64, C.c_void_p]),
+    "dmrg_iso_free": (None, [C.c_void_p]),
     "dmrg_opset_free": (None, [C.c_void_p]),
     "dmrg_heff_free": (None, [C.c_void_p]),
 }
@@ -200,6 +210,49 @@ class Isometry:
                        self._rows.ctypes.data_as(C.POINTER(C.c_int64)),
                        self._cols.ctypes.data_as(C.POINTER(C.c_int64)),
                        self._offs.ctypes.data_as(C.POINTER(C.c_int64)), DMRG_F64, C.c_void_p(ptr))
+
+
+class DecimatedIsometry:
+    """An isometry made by dmrg_decimate, held in the context arena; usable
+    wherever an Isometry is (its .bsm)."""
+
+    def __init__(self, ctx: "Context", ptr: C.c_void_p, info: DecimInfo):
+        self.ctx = ctx
+        self.ptr = ptr
+        self.info = {f: getattr(info, f) for f, _ in DecimInfo._fields_}
+        self.bsm = Bsm()
+        _check(load().dmrg_iso_bsm(self.ptr, C.byref(self.bsm)))
+
+    @property
+    def dims(self) -> Dict[Tuple[int, int], int]:
+        b = self.bsm
+        return {(b.qn_col[2 * i], b.qn_col[2 * i + 1]): int(b.cols[i]) for i in range(b.n_blocks)}
+
+    def weights(self) -> np.ndarray:
+        lib = load()
+        n = lib.dmrg_iso_weights(self.ptr, 0, None)
+        w = np.zeros(n)
+        lib.dmrg_iso_weights(self.ptr, n, w.ctypes.data_as(C.c_void_p))
+        return w
+
+    def to_host(self) -> Dict[Tuple[int, int], np.ndarray]:
+        """{q: U_q} copied to the host (device bytes read through the arena tensor)."""
+        import torch
+        b = self.bsm
+        base = self.ctx.arena.data_ptr()
+        off0 = b.data - base
+        n = sum(int(b.rows[i]) * int(b.cols[i]) for i in range(b.n_blocks))
+        flat = self.ctx.arena[off0:off0 + 8 * n].view(torch.float64).cpu().numpy()
+        out = {}
+        for i in range(b.n_blocks):
+            o, r, c = int(b.offset[i]), int(b.rows[i]), int(b.cols[i])
+            out[(b.qn_col[2 * i], b.qn_col[2 * i + 1])] = flat[o:o + r * c].reshape(r, c).copy()
+        return out
+
+    def free(self):
+        if self.ptr:
+            load().dmrg_iso_free(self.ptr)
+            self.ptr = None
 
 
 class OpSet:
@@ -324,6 +377,18 @@ class Heff:
         lib.dmrg_heff_psi_layout(self.ptr, n, ptr(ql), ptr(s1), ptr(s2), ptr(qr), ptr(rows), ptr(cols), ptr(off))
         return [((int(ql[2 * i]), int(ql[2 * i + 1])), int(s1[i]), int(s2[i]), (int(qr[2 * i]), int(qr[2 * i + 1])),
                  int(rows[i]), int(cols[i]), int(off[i])) for i in range(n)]
+
+    def decimate(self, psi, side: int = DMRG_LEFT, max_states: int = 0, n_vec: int = 1, noise: float = 0.0,
+                 xi=None) -> DecimatedIsometry:
+        """dmrg_decimate: the new basis of the block that moves on (side)."""
+        import torch
+        assert psi.dtype == torch.float64 and psi.is_cuda
+        out = C.c_void_p()
+        info = DecimInfo()
+        xp = C.c_void_p(xi.data_ptr()) if xi is not None else None
+        _check(load().dmrg_decimate(self.ptr, side, n_vec, C.c_void_p(psi.data_ptr()), float(noise), xp,
+                                    int(max_states), C.byref(out), C.byref(info), _stream(torch)))
+        return DecimatedIsometry(self.ctx, out, info)
 
     def renormalize(self, iso: Isometry) -> OpSet:
         """The blocked L' operators transformed through the isometry adding d1."""

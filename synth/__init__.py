@@ -381,9 +381,3 @@ def sweep_seed(inp: SweepInputs, sweep: int, backward: bool, KL: int) -> int:
     """Seed of the Davidson start vector at one step of a sweep."""
     return inp.seed_base + 10 + 1000 * sweep + 2 * KL + (1 if backward else 0)
 
-
-def unit_vector(dim: int, seed: int, n: int = 1) -> np.ndarray:
-    """n seeded Gaussian vectors of length dim, each of unit norm ([n, dim])."""
-    rng = np.random.default_rng(seed)
-    x = rng.standard_normal((n, dim))
-    return x / np.linalg.norm(x, axis=1, keepdims=True)

@@ -101,14 +101,18 @@ def test_two_roots_average_density_matrix(middle):
     _same_spectrum(d.all_weights, s ** 2)
 
 
-def test_noise_perturbs_psi_before_the_density_matrix(middle):
+def test_noise_adds_the_perturbation_density_matrix(middle):
     p, H = middle
     rng = np.random.default_rng(6)
     xi = rng.standard_normal(H.dim)
-    D, _, _ = _dense(H, p.psi + 1e-3 * xi)
-    s = np.linalg.svd(D, compute_uv=False)
+    D, _, _ = _dense(H, p.psi)
+    X, _, _ = _dense(H, xi)
+    s = np.linalg.svd(np.hstack([D, np.sqrt(1e-3) * X]), compute_uv=False)
     d = osw.decimate(H, [p.psi], "left", None, noise=1e-3, xis=[xi])
     _same_spectrum(d.all_weights, s ** 2)
+    # independent of the sign of the root
+    d2 = osw.decimate(H, [-p.psi], "left", None, noise=1e-3, xis=[xi])
+    np.testing.assert_allclose(d2.all_weights, d.all_weights, atol=1e-15)
 
 
 def test_kept_set_completes_multiplets_and_drops_weightless_states():
@@ -123,7 +127,7 @@ def test_kept_set_completes_multiplets_and_drops_weightless_states():
 
 
 def _run(inp, n_sweeps, M):
-    return osw.sweeps(inp, n_sweeps, lambda dim, seed, n: synth.unit_vector(dim, seed, n), M=M,
+    return osw.sweeps(inp, n_sweeps, lambda dim, seed, n: synth.random_vectors(dim, n, seed), M=M,
                       seed_of=lambda sw, b, KL: synth.sweep_seed(inp, sw, b, KL))
 
 
