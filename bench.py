@@ -140,7 +140,8 @@ def summarize_profile(d: str):
     run (kernel_stats.csv: calls and durations; counter_collection.csv:
     per-dispatch counter means over the H_eff product dispatches, i.e. every float
     chain kernel and the double ones dispatched after the first of them; the
-    copy kernels of the HBM-counter calibration are kept)."""
+    calibration kernel of the HBM counters, an elementwise negation over 1 GiB, is
+    kept)."""
     import collections
     import csv
     import glob
@@ -157,7 +158,7 @@ def summarize_profile(d: str):
             out.append(f"# {base}")
             for r in csv.DictReader(open(f)):
                 name = short(r.get("Name", ""))
-                if any(c in name for c in chain) or "copy" in name.lower():
+                if any(c in name for c in chain) or "neg_kernel" in name:
                     out.append(f"{name}; calls={r.get('Calls')}; total_ns={r.get('TotalDurationNs')}; "
                                f"avg_ns={r.get('AverageNs')}; min_ns={r.get('MinNs')}; max_ns={r.get('MaxNs')}")
         if base.endswith("counter_collection.csv"):
@@ -170,7 +171,7 @@ def summarize_profile(d: str):
                 name = short(r["Kernel_Name"])
                 did = int(r["Dispatch_Id"])
                 keep = any(c in name for c in chain) and first is not None and did >= first
-                if not (keep or "copy" in name.lower()):
+                if not (keep or "neg_kernel" in name):
                     continue
                 agg[name][r["Counter_Name"]] += float(r["Counter_Value"])
                 disp[name].add(did)
@@ -182,9 +183,55 @@ def summarize_profile(d: str):
     print("\n".join(out))
 
 
+def _counter_means(d: str, counter: str):
+    """Per-dispatch means of one counter over the product dispatches (as in
+    summarize_profile), by kernel name."""
+    import contextlib
+    import io
+    buf = io.StringIO()
+    with contextlib.redirect_stdout(buf):
+        summarize_profile(d)
+    out = {}
+    for line in buf.getvalue().splitlines():
+        if line.startswith("#") or f"{counter}=" not in line:
+            continue
+        name = line.split(";")[0]
+        for f in line.split(";"):
+            if f.strip().startswith(f"{counter}="):
+                out[name] = float(f.split("=")[1])
+    return out
+
+
+def traffic_summary(fetch_dir: str, write_dir: str, cal_bytes: int = 1 << 30):
+    """HBM bytes per launch of every product kernel from a FETCH_SIZE run and a
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter reads
+    for the calibration kernel (an elementwise negation reading and writing
+    cal_bytes); printed in the form counted_traffic reads."""
+    import hashlib
+    fe, wr = _counter_means(fetch_dir, "FETCH_SIZE"), _counter_means(write_dir, "WRITE_SIZE")
+    cal = [n for n in fe if "neg_kernel" in n]
+    if not cal or cal[0] not in wr:
+        raise SystemExit("calibration kernel missing from the counter runs")
+    kf = cal_bytes / (fe[cal[0]] * 1024.0)
+    kw = cal_bytes / (wr[cal[0]] * 1024.0)
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    print(f"kernels.hip sha256: {sha}")
+    print(f"calibration: {cal[0][:60]}...; FETCH_SIZE={fe[cal[0]]:.6g} KiB; WRITE_SIZE={wr[cal[0]]:.6g} KiB "
+          f"for {cal_bytes} bytes each way; factor_fetch={kf:.4f}; factor_write={kw:.4f}")
+    for n in sorted(fe):
+        if n in cal or n not in wr:
+            continue
+        rb, wb = fe[n] * 1024.0 * kf, wr[n] * 1024.0 * kw
+        print(f"kernel: name={n}; fetch_kib={fe[n]:.6g}; write_kib={wr[n]:.6g}; read_bytes={rb:.4g}; "
+              f"write_bytes={wb:.4g}; hbm_bytes_per_launch={rb + wb:.6g}")
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profile":
         summarize_profile(sys.argv[2])
+        return
+    if len(sys.argv) == 4 and sys.argv[1] == "--traffic":
+        traffic_summary(sys.argv[2], sys.argv[3])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,14 +336,15 @@ def main():
     if args.profile_apply:
         ts = timed_apply(dmrg.DMRG_PREC_F32, args.profile_apply)
         ts64 = timed_apply(dmrg.DMRG_PREC_F64, args.profile_apply)
-        # calibration for the HBM byte counters: a plain copy of 1 GiB (read 1 GiB, write 1 GiB)
+        # calibration for the HBM byte counters: an elementwise kernel of its own name
+        # (negation) over 1 GiB: reads 1 GiB, writes 1 GiB
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"profile_apply_ms_f32": ts, "profile_apply_ms_f64": ts64, "flops": F,
-                          "copy_bytes_each_way": src.numel() * 4}), flush=True)
+                          "calibration_kernel": "neg", "calibration_bytes_each_way": src.numel() * 4}), flush=True)
         return
 
     # ---- H_eff psi products (value), per-launch profile (roofline)

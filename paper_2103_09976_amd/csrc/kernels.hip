@@ -137,6 +137,22 @@ __device__ inline void unit_vec(int nvec, int& unit, int& vec) {
 inline unsigned grid_units(int units, int nvec) {
     return nvec == 1 ? (unsigned)units : (unsigned)((units + 7) / 8 * 8 * nvec);
 }
+// Tall tasks: the nct column slices (and the nvec vectors) of one task run on
+// workgroups of one XCD.  Workgroup L takes task ((L/8) / (nct*nvec))*8 + L%8
+// and, within it, sub-unit (L/8) % (nct*nvec) = vec*nct + slice, so the psi
+// rows and left-operator blocks every slice of the task reads are fetched into
+// that XCD's L2 once rather than once per slice.  Tasks still go to the XCDs
+// in turn, in list order.
+__device__ inline void tall_unit(int nct, int nvec, int& task, int& slice, int& vec) {
+    const int L = blockIdx.x;
+    const int m = nct * nvec;
+    const int local = L >> 3;
+    const int sub = local % m;
+    task = (local / m) * 8 + (L & 7);
+    slice = sub % nct;
+    vec = sub / nct;
+}
+inline unsigned grid_tall(int ntask, int nct, int nvec) { return (unsigned)((ntask + 7) / 8 * 8 * nct * nvec); }
 
 // ---------------------------------------------------------------------------
 // slice_kernel: output tiles of <= 96 rows x 16*NCT columns.  Every wave
@@ -414,6 +430,80 @@ __global__ __launch_bounds__(256, (SliceOcc<T, RT>::waves)) void slice_kernel(Ba
 // wave writes was last read before the previous barrier); FP64 keeps one
 // buffer and a second barrier, which leaves LDS for three workgroups per CU.
 // ---------------------------------------------------------------------------
+// Straight-line chunk loops of the tall kernel's common cases, for a wave
+// that owns NT row tiles (a compile-time count, so the loop has no per-tile
+// branch and the memory-count waits can be partial: the products of the
+// first tiles start while later tiles' fragments are still in flight).
+// U formation with A row-major and B transposed (a psi block times a right
+// operator block), over the full 16-k chunks; lanes outside the operand read
+// its element 0 and a zero factor (B) or the later row mask (A) clears them.
+template <typename T, int RW, int NT>
+__device__ __forceinline__ void tall_u_fast(typename Mfma<T>::v4 (&U)[RW], const T* Ap, const T* Bp, int lda,
+                                            int ldb, int kfull, int wv, int mu, int lr, int lk, int gcol,
+                                            bool colok, T alpha) {
+    const T acol = colok ? alpha : T(0);
+    uint32_t boff = colok ? (uint32_t)(gcol * ldb + 4 * lk) : 0u;
+    const uint32_t bstep = colok ? 16u : 0u;
+    uint32_t aoff[NT], astep[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int row = 16 * (wv + 4 * t) + lr;
+        const bool rok = row < mu;
+        aoff[t] = rok ? (uint32_t)(row * lda + 4 * lk) : 0u;
+        astep[t] = rok ? 16u : 0u;
+    }
+    for (int k0 = 0; k0 < kfull; k0 += 16) {
+        T fb[4], fa[NT][4];
+        ld4_at(Bp, boff, fb);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) ld4_at(Ap, aoff[t], fa[t]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) fb[s] *= acol;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) U[t] = Mfma<T>::mma(fa[t][s], fb[s], U[t]);
+            aoff[t] += astep[t];
+        }
+        boff += bstep;
+    }
+}
+
+// X . U with X row-major over the full 16-row chunks of U (U^T in LDS at su,
+// row stride LD); output rows at or beyond m accumulate values never stored.
+template <typename T, int RW, int NT, int LD>
+__device__ __forceinline__ void tall_x_fast(typename Mfma<T>::v4 (&acc)[RW], const T* Xp, int ldx, int qfull,
+                                            const T* su, int wv, int m, int lr, int lk) {
+    uint32_t xoff[NT], xstep[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int row = 16 * (wv + 4 * t) + lr;
+        const bool rok = row < m;
+        xoff[t] = rok ? (uint32_t)(row * ldx + 4 * lk) : 0u;
+        xstep[t] = rok ? 16u : 0u;
+    }
+    const T* p = su + lr * LD + 4 * lk;
+    for (int q = 0; q < qfull; ++q) {
+        T ub[4], xf[NT][4];
+        if constexpr (sizeof(T) == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(p + 16 * q);
+            ub[0] = v.x; ub[1] = v.y; ub[2] = v.z; ub[3] = v.w;
+        } else {
+            const double2 a = *reinterpret_cast<const double2*>(p + 16 * q);
+            const double2 b = *reinterpret_cast<const double2*>(p + 16 * q + 2);
+            ub[0] = a.x; ub[1] = a.y; ub[2] = b.x; ub[3] = b.y;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) ld4_at(Xp, xoff[t], xf[t]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[t] = Mfma<T>::mma(xf[t][s], ub[s], acc[t]);
+            xoff[t] += xstep[t];
+        }
+    }
+}
+
 template <typename T> struct TallCfg;
 template <> struct TallCfg<float> {
     static constexpr int nbuf = 2, ld = kTallRows + 4, waves = 3;
@@ -438,18 +528,20 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
     __shared__ Contrib sC[LR ? kRecC : 1];
     (void)Bargs;
 
-    int unit, vec;
-    unit_vec(nvec, unit, vec);
-    if (unit >= ntask * NCT) return;         // the whole workgroup: no barrier is reached
+    int task, w, vec;
+    tall_unit(NCT, nvec, task, w, vec);
+    if (task >= ntask) return;               // the whole workgroup: no barrier is reached
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wv = tid >> 6;
-    const int w = unit % NCT;                // column slice of the task
-    const Task tk = tasks[unit / NCT];
+    // the wave index in a scalar register: the per-tile guards below are then
+    // scalar branches, not exec-mask changes
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const Task tk = tasks[task];
     const int lr0 = lane & 15;
     const int lk0 = lane >> 4;
     const int ncv = min(tk.ncol, tk.n - tk.col0);
     const int nrm = (tk.m + 15) >> 4;
+    const int nto = nrm > wv ? (nrm - wv + 3) >> 2 : 0;   // output row tiles of this wave
     Recs<LR> R;
     if constexpr (LR) {
         const int cb = stage_records(groups, contribs, tk.g0, tk.g1, sG, sC, tid, 256);
@@ -469,6 +561,7 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
         const Group gr = R.group(g);
         const int mu = gr.mu;
         const int nru = (mu + 15) >> 4;
+        const int ntu = nru > wv ? (nru - wv + 3) >> 2 : 0;   // U row tiles of this wave
         V4 U[RW];
 #pragma unroll
         for (int t = 0; t < RW; ++t) U[t] = V4{0, 0, 0, 0};
@@ -510,7 +603,26 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             const T* Bp = base_ptr<T>((ct.flags >> 3) & 7, vec) + ct.b_off;
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
-            for (int k0 = 0; k0 < K; k0 += 16) {
+            int kstart = 0;
+            if (sizeof(T) == 4 && !ta && tb) {   // the common case, over the full chunks (FP32: the
+                                                 // FP64 fragments of five tiles would not fit registers)
+                const int kfull = K & ~15;
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                const int gcol = tk.col0 + 16 * w + lr;
+                const bool colok = 16 * w + lr < ncv;
+                if (kfull > 0) {
+                    switch (ntu) {
+                        case 1: tall_u_fast<T, RW, 1>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
+                        case 2: tall_u_fast<T, RW, 2>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
+                        case 3: tall_u_fast<T, RW, 3>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
+                        case 4: tall_u_fast<T, RW, 4>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
+                        case 5: tall_u_fast<T, RW, 5>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
+                        default: break;
+                    }
+                }
+                kstart = kfull;
+            }
+            for (int k0 = kstart; k0 < K; k0 += 16) {
                 T fa[RW][4], fb[4];
                 {
                     const int lr = opaque(lr0), lk = opaque(lk0);
@@ -518,6 +630,18 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
                     const bool colok = 16 * w + lr < ncv;
                     const int kb = k0 + 4 * lk;
                     const bool vec4 = k0 + 16 <= K;
+                    // B first: every tile's MFMAs need it, so the A loads behind it can
+                    // still be in flight when the first tile's products start
+                    if (tb && vec4) {
+                        ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + kb) : 0u, fb);
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int k = kb + s;
+                            const bool ok = colok && k < K;
+                            fb[s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gcol * ldb + k) : (uint32_t)(k * ldb + gcol)) : 0u);
+                        }
+                    }
 #pragma unroll
                     for (int t = 0; t < RW; ++t) {
                         const int j = wv + 4 * t;
@@ -535,18 +659,16 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
                             }
                         }
                     }
-                    if (tb && vec4) {
-                        ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + kb) : 0u, fb);
+                    // loads at masked positions read element 0 of the operand (finite), so
+                    // a zero factor clears them; the k mask matters only in the last chunk
+                    const T acol = colok ? alpha : T(0);
+                    if (vec4) {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) fb[s] *= acol;
                     } else {
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            const int k = kb + s;
-                            const bool ok = colok && k < K;
-                            fb[s] = ld_at(Bp, ok ? (tb ? (uint32_t)(gcol * ldb + k) : (uint32_t)(k * ldb + gcol)) : 0u);
-                        }
+                        for (int s = 0; s < 4; ++s) fb[s] = kb + s < K ? acol * fb[s] : T(0);
                     }
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) fb[s] = (colok && kb + s < K) ? alpha * fb[s] : T(0);
                 }
 #pragma unroll
                 for (int t = 0; t < RW; ++t) {
@@ -586,7 +708,23 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             const T* Xp = base_ptr<T>(gr.flags & 7, vec) + gr.x_off;
             const bool tx = (gr.flags & G_TRANS_X) != 0;
             const int ldx = gr.ldx;
-            for (int q = 0; q < nru; ++q) {
+            int qstart = 0;
+            if (sizeof(T) == 4 && !tx) {   // row-major X over the full 16-row chunks of U
+                const int qfull = mu >> 4;
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                if (qfull > 0) {
+                    switch (nto) {
+                        case 1: tall_x_fast<T, RW, 1, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
+                        case 2: tall_x_fast<T, RW, 2, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
+                        case 3: tall_x_fast<T, RW, 3, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
+                        case 4: tall_x_fast<T, RW, 4, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
+                        case 5: tall_x_fast<T, RW, 5, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
+                        default: break;
+                    }
+                }
+                qstart = qfull;
+            }
+            for (int q = qstart; q < nru; ++q) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 // B fragment: U[16q + 4 lk + s][lr], s = 0..3 (four consecutive k of U^T's row lr)
                 T ub[4];
@@ -904,7 +1042,8 @@ static KernelDesc chain_desc(int cls, bool lds_records, int ntask, int nvec) {
     KernelDesc d{};
     if (ntask <= 0 || cls < 0 || cls >= kNumClass) return d;
     d.func = lds_records ? chain_func<T, true>(cls) : chain_func<T, false>(cls);
-    d.gx = grid_units(chain_units(cls, ntask), nvec);
+    d.gx = cls >= kTallClass0 ? grid_tall(ntask, cls - kTallClass0 + 1, nvec)
+                              : grid_units(chain_units(cls, ntask), nvec);
     d.gy = 1;
     d.bx = 256;
     return d;
