@@ -245,11 +245,17 @@ def main():
     ap.add_argument("--profile-apply", type=int, default=0,
                     help="only build once and run this many FP32 and FP64 products (for profilers); no "
                          "tuning products run (set DMRG_BALANCE to the tuned choice of a bench run)")
+    ap.add_argument("--sweep", type=int, default=0,
+                    help="instead: this many two-site sweeps over the whole chain of the workload's shape "
+                         "(K, N, S_z, M; FP32-mixed Davidson to residual 1e-6), one JSON line of per-step times")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multi-GPU (sub-Hamiltonian) path is not part of this build",
               file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        sweep_bench(args)
+        return
 
     import torch
     import synth
@@ -466,6 +472,47 @@ def main():
         note("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(float(F * roots))
     print(json.dumps(out), flush=True)
+
+
+def sweep_bench(args):
+    """Two-site sweeps (decimation, renormalization, H_eff and Davidson at every
+    dot position) on the workload's shape with seeded inputs; prints one JSON
+    line with the per-step and total times."""
+    import torch
+    import synth
+    from paper_2103_09976_amd import dmrg, sweep as gsw
+    kw = dict(synth.CONFIGS[args.workload])
+    kw.pop("n_proc", None)
+    kw.pop("proc_id", None)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    inp = synth.make_sweep_inputs(kw["K"], kw["n_elec"], kw["two_sz"], kw["M"], kw["seed_base"] + 500)
+    ctx = dmrg.Context(int(torch.cuda.mem_get_info()[0] * 0.8))
+    rows = []
+
+    def on_step(st):
+        rows.append(st)
+        note(f"sweep {st.sweep} {'<-' if st.backward else '->'} KL={st.KL} dim={st.dim} E={st.energies[0]:.10f} "
+             f"kept={st.kept} iters={st.davidson.get('iters')} ms={ {k: round(v, 1) for k, v in st.ms.items()} }")
+    t0 = time.perf_counter()
+    gsw.run_sweeps(ctx, inp, args.sweep, kw["M"], lambda d, s, n: synth.random_vectors(d, n, s),
+                   lambda sw, b, KL: synth.sweep_seed(inp, sw, b, KL), tol=1e-6, precision=dmrg.DMRG_PREC_F32,
+                   max_iter=300, on_step=on_step)
+    wall = time.perf_counter() - t0
+    ctx.close()
+    tot = {k: round(sum(r.ms.get(k, 0.0) for r in rows), 1) for k in ("heff_create", "davidson", "decimate",
+                                                                      "renormalize")}
+    print(json.dumps({
+        "mode": "sweep", "workload": f"{args.workload} shape, whole chain: K={kw['K']}, N={kw['n_elec']}, "
+                                     f"2S_z={kw['two_sz']}, M={kw['M']}",
+        "sweeps": args.sweep, "steps": len(rows), "wall_s": round(wall, 2), "ms_totals": tot,
+        "energies_last_half_sweep": [r.energies[0] for r in rows if r.sweep == args.sweep - 1 and r.backward],
+        "final_energy": rows[-1].energies[0] if rows else None,
+        "max_trunc_err_last_sweep": max((r.trunc_err for r in rows if r.sweep == args.sweep - 1), default=None),
+        "steps_detail": [{"sweep": r.sweep, "backward": r.backward, "KL": r.KL, "dim": r.dim, "E": r.energies[0],
+                          "kept": r.kept, "trunc_err": r.trunc_err, "iters": r.davidson.get("iters"),
+                          "ms": {k: round(v, 2) for k, v in r.ms.items()}} for r in rows],
+    }), flush=True)
 
 
 def roofline(launches, F, workload):

@@ -309,9 +309,10 @@ dmrg_status dmrg_renormalize(dmrg_ctx* ctx, const dmrg_opset* in, const dmrg_bsm
  *     caller's perturbations (xi[n_vec * dim], device, in H's layout; ignored
  *     when noise == 0): positive semidefinite, independent of the roots' signs;
  *   max_states: M, the states to keep (<= 0: no limit).  Kept are the M
- *     largest weights over all sectors, plus every state within 1e-8 w_max
- *     of the M-th (no multiplet of the spin symmetry is cut), minus every
- *     state of weight <= 1e-14 w_max (w_max the largest weight).
+ *     largest weights over all sectors, plus every state within 1e-5 w_M +
+ *     1e-12 w_max of the M-th weight w_M (no multiplet of the spin symmetry
+ *     is cut), minus every state of weight <= 1e-14 w_max (w_max the
+ *     largest weight).
  * The density matrices are GEMMs on the library's FP64 MFMA kernels; each
  * sector's is diagonalised with rocSOLVER (dsyevd), its workspace taken from
  * the arena.  *out: the isometry, columns by descending weight within each

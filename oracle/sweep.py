@@ -18,11 +18,12 @@ Readings fixed here (the paper does not spell them out):
   a given perturbation Xi: a positive semidefinite term that does not depend
   on the sign of a root;
 * kept states: the M largest weights over all sectors, plus every further
-  state whose weight lies within tie_rel * w_max of the M-th (so no
-  multiplet of the spin symmetry is cut, also when a solver's residual
-  splits it slightly), minus every state of weight at most floor_rel *
-  w_max (no basis state without weight is kept); with M None, or M at
-  least the number of states above that floor, every such state is kept;
+  state whose weight lies within tie_rel * w_M + tie_abs * w_max of the M-th
+  weight w_M (so no multiplet of the spin symmetry is cut, also when a
+  solver's residual splits it slightly, while the bond dimension stays M up
+  to such partners), minus every state of weight at most floor_rel * w_max
+  (no basis state without weight is kept); with M None, or M at least the
+  number of states above that floor, every such state is kept;
 * truncation error: discarded weight / total weight;
 * each step solves for the lowest root(s) of H_eff from a seeded start
   vector; the last step of a half-sweep is solved again at the start of the
@@ -66,12 +67,13 @@ def density_matrices(H: TwoSiteHeff, psis: List[np.ndarray], side: str, noise: f
     return {q: r / len(psis) for q, r in sorted(rho.items())}
 
 
-TIE_REL = 1e-8
+TIE_REL = 1e-5
+TIE_ABS = 1e-12
 FLOOR_REL = 1e-14
 
 
 def select_states(rho: Dict[Q, np.ndarray], M: Optional[int], tie_rel: float = TIE_REL,
-                  floor_rel: float = FLOOR_REL) -> Decimation:
+                  floor_rel: float = FLOOR_REL, tie_abs: float = TIE_ABS) -> Decimation:
     """Diagonalise each sector's density matrix and keep the heaviest states."""
     eig = {}
     allw = []
@@ -86,7 +88,8 @@ def select_states(rho: Dict[Q, np.ndarray], M: Optional[int], tie_rel: float = T
     if M is None or M >= int(np.sum(allw > floor)):
         cut = floor
     else:
-        cut = max(float(allw[M - 1]) - tie_rel * wmax, floor)
+        wM = float(allw[M - 1])
+        cut = max(wM - tie_rel * wM - tie_abs * wmax, floor)
     U, dims, wk = {}, {}, {}
     kept_w = 0.0
     for q, (w, V) in eig.items():

@@ -48,10 +48,13 @@ using namespace dmrg;
 namespace {
 
 // Kept states: the max_states heaviest over all sectors, extended by every
-// state within kTieRel * w_max of the last one (no multiplet of the spin
-// symmetry is cut, also when a solver's residual splits it slightly), and
-// no state of weight <= kFloorRel * w_max (no weightless basis state).
-constexpr double kTieRel = 1e-8;
+// state within kTieRel * w_M + kTieAbs * w_max of the last one's weight w_M
+// (no multiplet of the spin symmetry is cut, also when a solver's residual
+// splits it slightly, and the bond dimension stays max_states up to such
+// partners), and no state of weight <= kFloorRel * w_max (no weightless
+// basis state).
+constexpr double kTieRel = 1e-5;
+constexpr double kTieAbs = 1e-12;
 constexpr double kFloorRel = 1e-14;
 
 struct Sector {
@@ -325,7 +328,7 @@ dmrg_status dmrg_decimate(dmrg_heff* H, int32_t side, int32_t n_vec, const doubl
     std::sort(sorted.begin(), sorted.end(), std::greater<double>());
     double cut = floor;
     if (max_states > 0 && (size_t)max_states < sorted.size())
-        cut = std::max(sorted[max_states - 1] - kTieRel * wmax, floor);
+        cut = std::max(sorted[max_states - 1] * (1.0 - kTieRel) - kTieAbs * wmax, floor);
     auto keep = [&](double x) { return cut <= floor ? x > floor : x >= cut; };
 
     dmrg_iso* iso = new dmrg_iso();

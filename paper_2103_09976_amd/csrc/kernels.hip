@@ -137,22 +137,29 @@ __device__ inline void unit_vec(int nvec, int& unit, int& vec) {
 inline unsigned grid_units(int units, int nvec) {
     return nvec == 1 ? (unsigned)units : (unsigned)((units + 7) / 8 * 8 * nvec);
 }
-// Tall tasks: the nct column slices (and the nvec vectors) of one task run on
-// workgroups of one XCD.  Workgroup L takes task ((L/8) / (nct*nvec))*8 + L%8
-// and, within it, sub-unit (L/8) % (nct*nvec) = vec*nct + slice, so the psi
-// rows and left-operator blocks every slice of the task reads are fetched into
-// that XCD's L2 once rather than once per slice.  Tasks still go to the XCDs
-// in turn, in list order.
+// Tall tasks: the nct column slices (and the nvec vectors) of one task, and
+// runs of kTallRun consecutive tasks, run on workgroups of one XCD.  Column
+// tiles of one output block are consecutive in the list (equal cost, stable
+// order) and read the same psi rows and left-operator blocks, so those are
+// fetched into that XCD's L2 once rather than once per slice or tile.
+// Workgroup L (the XCD is L % 8) takes, with local = L / 8, m = nct*nvec and
+// r = local / m: task ((r / kTallRun)*8 + L%8)*kTallRun + r % kTallRun, and
+// sub-unit local % m = vec*nct + slice.  Runs go to the XCDs in turn, in list
+// order.
+constexpr int kTallRun = 4;
 __device__ inline void tall_unit(int nct, int nvec, int& task, int& slice, int& vec) {
     const int L = blockIdx.x;
     const int m = nct * nvec;
     const int local = L >> 3;
     const int sub = local % m;
-    task = (local / m) * 8 + (L & 7);
+    const int r = local / m;
+    task = ((r / kTallRun) * 8 + (L & 7)) * kTallRun + r % kTallRun;
     slice = sub % nct;
     vec = sub / nct;
 }
-inline unsigned grid_tall(int ntask, int nct, int nvec) { return (unsigned)((ntask + 7) / 8 * 8 * nct * nvec); }
+inline unsigned grid_tall(int ntask, int nct, int nvec) {
+    return (unsigned)((ntask + 8 * kTallRun - 1) / (8 * kTallRun) * 8 * kTallRun * nct * nvec);
+}
 
 // ---------------------------------------------------------------------------
 // slice_kernel: output tiles of <= 96 rows x 16*NCT columns.  Every wave
@@ -604,8 +611,9 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
             int kstart = 0;
-            if (sizeof(T) == 4 && !ta && tb) {   // the common case, over the full chunks (FP32: the
-                                                 // FP64 fragments of five tiles would not fit registers)
+            // the common case, over the full chunks (FP64 up to three tiles per wave: the
+            // FP64 fragments of four or five would not fit the registers)
+            if ((sizeof(T) == 4 || ntu <= 3) && !ta && tb) {
                 const int kfull = K & ~15;
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const int gcol = tk.col0 + 16 * w + lr;
@@ -615,8 +623,14 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
                         case 1: tall_u_fast<T, RW, 1>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
                         case 2: tall_u_fast<T, RW, 2>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
                         case 3: tall_u_fast<T, RW, 3>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
-                        case 4: tall_u_fast<T, RW, 4>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
-                        case 5: tall_u_fast<T, RW, 5>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
+                        case 4:
+                            if constexpr (sizeof(T) == 4)
+                                tall_u_fast<T, RW, 4>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha);
+                            break;
+                        case 5:
+                            if constexpr (sizeof(T) == 4)
+                                tall_u_fast<T, RW, 5>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha);
+                            break;
                         default: break;
                     }
                 }
@@ -709,7 +723,7 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             const bool tx = (gr.flags & G_TRANS_X) != 0;
             const int ldx = gr.ldx;
             int qstart = 0;
-            if (sizeof(T) == 4 && !tx) {   // row-major X over the full 16-row chunks of U
+            if ((sizeof(T) == 4 || nto <= 3) && !tx) {   // row-major X over the full 16-row chunks of U
                 const int qfull = mu >> 4;
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 if (qfull > 0) {
@@ -717,8 +731,12 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
                         case 1: tall_x_fast<T, RW, 1, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
                         case 2: tall_x_fast<T, RW, 2, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
                         case 3: tall_x_fast<T, RW, 3, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
-                        case 4: tall_x_fast<T, RW, 4, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
-                        case 5: tall_x_fast<T, RW, 5, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
+                        case 4:
+                            if constexpr (sizeof(T) == 4) tall_x_fast<T, RW, 4, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                            break;
+                        case 5:
+                            if constexpr (sizeof(T) == 4) tall_x_fast<T, RW, 5, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                            break;
                         default: break;
                     }
                 }
