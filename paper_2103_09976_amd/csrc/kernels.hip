@@ -459,20 +459,46 @@ __device__ __forceinline__ void tall_u_fast(typename Mfma<T>::v4 (&U)[RW], const
         aoff[t] = rok ? (uint32_t)(row * lda + 4 * lk) : 0u;
         astep[t] = rok ? 16u : 0u;
     }
-    for (int k0 = 0; k0 < kfull; k0 += 16) {
-        T fb[4], fa[NT][4];
+    // FP32 is software-pipelined: the next chunk's fragments are requested
+    // before this chunk's products, so each wave keeps two chunks of loads in
+    // flight (FP64 has no registers for a second set)
+    constexpr bool pipe = sizeof(T) == 4 && NT <= 4;
+    T fb[4], fa[NT][4];
+    if constexpr (pipe) {
         ld4_at(Bp, boff, fb);
 #pragma unroll
         for (int t = 0; t < NT; ++t) ld4_at(Ap, aoff[t], fa[t]);
+    }
+    for (int k0 = 0; k0 < kfull; k0 += 16) {
+        if constexpr (!pipe) {
+            ld4_at(Bp, boff, fb);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ld4_at(Ap, aoff[t], fa[t]);
+        }
+        T nb[4], na[NT][4];
+        const bool more = pipe && k0 + 16 < kfull;
+        boff += bstep;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) aoff[t] += astep[t];
+        if (more) {
+            ld4_at(Bp, boff, nb);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ld4_at(Ap, aoff[t], na[t]);
+        }
 #pragma unroll
         for (int s = 0; s < 4; ++s) fb[s] *= acol;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int s = 0; s < 4; ++s) U[t] = Mfma<T>::mma(fa[t][s], fb[s], U[t]);
-            aoff[t] += astep[t];
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) fb[s] = nb[s];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) fa[t][s] = na[t][s];
         }
-        boff += bstep;
     }
 }
 
@@ -509,6 +535,52 @@ __device__ __forceinline__ void tall_x_fast(typename Mfma<T>::v4 (&acc)[RW], con
             xoff[t] += xstep[t];
         }
     }
+}
+
+// The partial last chunks of both loops, as vector loads: lane group g takes
+// the four k at kb = min(k0 + 4g, K - 4), which lie inside the operand, and a
+// zero B (or U) factor drops the k below k0 + 4g that the previous group
+// covers.  Needs K >= 4.
+template <typename T, int RW, int NT>
+__device__ __forceinline__ void tall_u_tail(typename Mfma<T>::v4 (&U)[RW], const T* Ap, const T* Bp, int lda,
+                                            int ldb, int k0, int K, int wv, int mu, int lr, int lk, int gcol,
+                                            bool colok, T alpha) {
+    const int kk = k0 + 4 * lk;
+    const int kb = min(kk, K - 4);
+    T fb[4], fa[NT][4];
+    ld4_at(Bp, colok ? (uint32_t)(gcol * ldb + kb) : 0u, fb);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int row = 16 * (wv + 4 * t) + lr;
+        ld4_at(Ap, row < mu ? (uint32_t)(row * lda + kb) : 0u, fa[t]);
+    }
+    const T acol = colok ? alpha : T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) fb[s] = kb + s >= kk ? acol * fb[s] : T(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) U[t] = Mfma<T>::mma(fa[t][s], fb[s], U[t]);
+}
+
+template <typename T, int RW, int NT, int LD>
+__device__ __forceinline__ void tall_x_tail(typename Mfma<T>::v4 (&acc)[RW], const T* Xp, int ldx, int k0, int mu,
+                                            const T* su, int wv, int m, int lr, int lk) {
+    const int kk = k0 + 4 * lk;
+    const int kb = min(kk, mu - 4);
+    T ub[4], xf[NT][4];
+    const T* p = su + lr * LD + kb;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) ub[s] = kb + s >= kk ? p[s] : T(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int row = 16 * (wv + 4 * t) + lr;
+        ld4_at(Xp, row < m ? (uint32_t)(row * ldx + kb) : 0u, xf[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[t] = Mfma<T>::mma(xf[t][s], ub[s], acc[t]);
 }
 
 template <typename T> struct TallCfg;
@@ -615,26 +687,40 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             // FP64 fragments of four or five would not fit the registers)
             if ((sizeof(T) == 4 || ntu <= 3) && !ta && tb) {
                 const int kfull = K & ~15;
+                const bool tail = kfull < K && K >= 4;   // the partial chunk as vector loads too
                 const int lr = opaque(lr0), lk = opaque(lk0);
                 const int gcol = tk.col0 + 16 * w + lr;
                 const bool colok = 16 * w + lr < ncv;
-                if (kfull > 0) {
+                if (kfull > 0 || tail) {
                     switch (ntu) {
-                        case 1: tall_u_fast<T, RW, 1>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
-                        case 2: tall_u_fast<T, RW, 2>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
-                        case 3: tall_u_fast<T, RW, 3>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha); break;
+                        case 1:
+                            tall_u_fast<T, RW, 1>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha);
+                            if (tail) tall_u_tail<T, RW, 1>(U, Ap, Bp, lda, ldb, kfull, K, wv, mu, lr, lk, gcol, colok, alpha);
+                            break;
+                        case 2:
+                            tall_u_fast<T, RW, 2>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha);
+                            if (tail) tall_u_tail<T, RW, 2>(U, Ap, Bp, lda, ldb, kfull, K, wv, mu, lr, lk, gcol, colok, alpha);
+                            break;
+                        case 3:
+                            tall_u_fast<T, RW, 3>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha);
+                            if (tail) tall_u_tail<T, RW, 3>(U, Ap, Bp, lda, ldb, kfull, K, wv, mu, lr, lk, gcol, colok, alpha);
+                            break;
                         case 4:
-                            if constexpr (sizeof(T) == 4)
+                            if constexpr (sizeof(T) == 4) {
                                 tall_u_fast<T, RW, 4>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha);
+                                if (tail) tall_u_tail<T, RW, 4>(U, Ap, Bp, lda, ldb, kfull, K, wv, mu, lr, lk, gcol, colok, alpha);
+                            }
                             break;
                         case 5:
-                            if constexpr (sizeof(T) == 4)
+                            if constexpr (sizeof(T) == 4) {
                                 tall_u_fast<T, RW, 5>(U, Ap, Bp, lda, ldb, kfull, wv, mu, lr, lk, gcol, colok, alpha);
+                                if (tail) tall_u_tail<T, RW, 5>(U, Ap, Bp, lda, ldb, kfull, K, wv, mu, lr, lk, gcol, colok, alpha);
+                            }
                             break;
                         default: break;
                     }
                 }
-                kstart = kfull;
+                kstart = tail ? K : kfull;
             }
             for (int k0 = kstart; k0 < K; k0 += 16) {
                 T fa[RW][4], fb[4];
@@ -725,22 +811,38 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             int qstart = 0;
             if ((sizeof(T) == 4 || nto <= 3) && !tx) {   // row-major X over the full 16-row chunks of U
                 const int qfull = mu >> 4;
+                const bool tail = 16 * qfull < mu && mu >= 4;
                 const int lr = opaque(lr0), lk = opaque(lk0);
-                if (qfull > 0) {
+                if (qfull > 0 || tail) {
                     switch (nto) {
-                        case 1: tall_x_fast<T, RW, 1, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
-                        case 2: tall_x_fast<T, RW, 2, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
-                        case 3: tall_x_fast<T, RW, 3, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk); break;
+                        case 1:
+                            tall_x_fast<T, RW, 1, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                            if (tail) tall_x_tail<T, RW, 1, LD>(acc, Xp, ldx, 16 * qfull, mu, su, wv, tk.m, lr, lk);
+                            break;
+                        case 2:
+                            tall_x_fast<T, RW, 2, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                            if (tail) tall_x_tail<T, RW, 2, LD>(acc, Xp, ldx, 16 * qfull, mu, su, wv, tk.m, lr, lk);
+                            break;
+                        case 3:
+                            tall_x_fast<T, RW, 3, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                            if (tail) tall_x_tail<T, RW, 3, LD>(acc, Xp, ldx, 16 * qfull, mu, su, wv, tk.m, lr, lk);
+                            break;
                         case 4:
-                            if constexpr (sizeof(T) == 4) tall_x_fast<T, RW, 4, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                            if constexpr (sizeof(T) == 4) {
+                                tall_x_fast<T, RW, 4, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                                if (tail) tall_x_tail<T, RW, 4, LD>(acc, Xp, ldx, 16 * qfull, mu, su, wv, tk.m, lr, lk);
+                            }
                             break;
                         case 5:
-                            if constexpr (sizeof(T) == 4) tall_x_fast<T, RW, 5, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                            if constexpr (sizeof(T) == 4) {
+                                tall_x_fast<T, RW, 5, LD>(acc, Xp, ldx, qfull, su, wv, tk.m, lr, lk);
+                                if (tail) tall_x_tail<T, RW, 5, LD>(acc, Xp, ldx, 16 * qfull, mu, su, wv, tk.m, lr, lk);
+                            }
                             break;
                         default: break;
                     }
                 }
-                qstart = qfull;
+                qstart = tail ? nru : qfull;
             }
             for (int q = qstart; q < nru; ++q) {
                 const int lr = opaque(lr0), lk = opaque(lk0);
