@@ -785,6 +785,28 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
             if (!w.empty())
                 std::fprintf(stderr, "[dmrg] class %d: tasks %zu work %.3f TF max %.3f GF median %.3f GF p99 %.3f GF\n", c,
                              w.size(), tot / 1e12, mx / 1e9, w[w.size() / 2] / 1e9, w[w.size() * 99 / 100] / 1e9);
+            // operand layouts of the class's products (flops): A.B with A row-major and B
+            // transposed, other A.B layouts, X.U with X row-major, X transposed; identities
+            double f_ab = 0, f_ab_other = 0, f_x = 0, f_xt = 0;
+            size_t n_id = 0;
+            for (const dmrgk::Task& t : wl.task[c]) {
+                const int cols = std::min(t.ncol, t.n - t.col0);
+                for (int g = t.g0; g < t.g1; ++g) {
+                    const dmrgk::Group& G = wl.groups[g];
+                    if (G.flags & dmrgk::G_HAS_X)
+                        ((G.flags & dmrgk::G_TRANS_X) ? f_xt : f_x) += 2.0 * t.m * G.mu * cols;
+                    for (int q = G.c0; q < G.c1; ++q) {
+                        const dmrgk::Contrib& k = wl.contribs[q];
+                        if (k.flags & (dmrgk::F_ID_A | dmrgk::F_ID_B)) { ++n_id; continue; }
+                        const bool fast = !(k.flags & dmrgk::F_TRANS_A) && (k.flags & dmrgk::F_TRANS_B);
+                        (fast ? f_ab : f_ab_other) += 2.0 * G.mu * k.k * cols;
+                    }
+                }
+            }
+            if (!w.empty())
+                std::fprintf(stderr, "[dmrg]   layouts: A.B row/trans %.3f TF, other %.3f TF; X.U row %.3f TF, "
+                             "trans %.3f TF; identity contributions %zu\n", f_ab / 1e12, f_ab_other / 1e12,
+                             f_x / 1e12, f_xt / 1e12, n_id);
         }
     }
     if (clk.on)

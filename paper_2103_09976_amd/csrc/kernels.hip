@@ -583,6 +583,71 @@ __device__ __forceinline__ void tall_x_tail(typename Mfma<T>::v4 (&acc)[RW], con
         for (int s = 0; s < 4; ++s) acc[t] = Mfma<T>::mma(xf[t][s], ub[s], acc[t]);
 }
 
+// U formation with A row-major and B row-major (a psi block times a right
+// operator used as its transpose): a lane's four k of B are a column of B,
+// four separate loads per lane.  Instead each chunk of B (16 k x 16 columns)
+// is read row-wise with one 16-byte load per lane, transposed through the
+// wave's own LDS scratch (16 x 16 floats, an array of its own: no other wave
+// touches it) and read back as one 16-byte LDS read per lane.  FP32, K >= 16; the last partial chunk restarts at K - 16
+// with the rows already summed zeroed in B.  Lanes outside the operand load
+// nothing (B) or element 0 (A, cleared by the later row mask).
+template <int RW, int NT>
+__device__ __forceinline__ void tall_u_rowB(typename Mfma<float>::v4 (&U)[RW], const float* Ap, const float* Bp,
+                                            int lda, int ldb, int K, int wv, int mu, int lr, int lk, int bcol0,
+                                            int ncolv, float alpha, float* scr) {
+    constexpr int SL = 16;                      // scratch row stride (16-byte aligned rows)
+    const int lane = lr + 16 * lk;
+    const int kr = lane >> 2, c4 = 4 * (lane & 3);
+    uint32_t abase[NT];
+    bool rok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int row = 16 * (wv + 4 * t) + lr;
+        rok[t] = row < mu;
+        abase[t] = rok[t] ? (uint32_t)(row * lda) : 0u;
+    }
+    const int kfull = K & ~15;
+    const int nch = kfull / 16 + (kfull < K ? 1 : 0);
+    for (int c = 0; c < nch; ++c) {
+        const bool last = c * 16 >= kfull;           // the partial chunk, restarted at K - 16
+        const int k0 = last ? K - 16 : c * 16;
+        const int kskip = last ? kfull - k0 : 0;     // rows already summed
+        // B rows k0 + kr, columns c4..c4+3 of the slice
+        float bq[4] = {0.f, 0.f, 0.f, 0.f};
+        if (kr >= kskip) {
+            const uint32_t o = (uint32_t)((k0 + kr) * ldb + bcol0 + c4);
+            if (c4 + 4 <= ncolv) {
+                ld4_at(Bp, o, bq);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (c4 + j < ncolv) bq[j] = ld_at(Bp, o + (uint32_t)j);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) scr[(c4 + j) * SL + kr] = alpha * bq[j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float fb[4];
+        {
+            const float4 v = *reinterpret_cast<const float4*>(scr + lr * SL + 4 * lk);
+            fb[0] = v.x; fb[1] = v.y; fb[2] = v.z; fb[3] = v.w;
+        }
+        float fa[NT][4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) ld4_at(Ap, rok[t] ? abase[t] + (uint32_t)(k0 + 4 * lk) : 0u, fa[t]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) U[t] = Mfma<float>::mma(fa[t][s], fb[s], U[t]);
+        // every lane's read of this chunk precedes the next chunk's writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 template <typename T> struct TallCfg;
 template <> struct TallCfg<float> {
     static constexpr int nbuf = 2, ld = kTallRows + 4, waves = 3;
@@ -603,6 +668,8 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
     constexpr int LD = TallCfg<T>::ld;
     constexpr int NB = TallCfg<T>::nbuf;
     __shared__ __attribute__((aligned(16))) T sU[NB][16 * LD];
+    // per-wave transposition scratch of the row-major B path (FP32 only)
+    __shared__ __attribute__((aligned(16))) float sBt[sizeof(T) == 4 ? 4 * 256 : 4];
     __shared__ Group sG[LR ? kRecG : 1];
     __shared__ Contrib sC[LR ? kRecC : 1];
     (void)Bargs;
@@ -683,6 +750,23 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
             int kstart = 0;
+            if constexpr (sizeof(T) == 4) {
+                if (!ta && !tb && K >= 16) {   // B row-major: through the wave's LDS scratch
+                    const int lr = opaque(lr0), lk = opaque(lk0);
+                    float* scr = sBt + wv * 256;
+                    const int ncolv = min(16, ncv - 16 * w);
+                    const int bc0 = tk.col0 + 16 * w;
+                    switch (ntu) {
+                        case 1: tall_u_rowB<RW, 1>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        case 2: tall_u_rowB<RW, 2>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        case 3: tall_u_rowB<RW, 3>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        case 4: tall_u_rowB<RW, 4>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        case 5: tall_u_rowB<RW, 5>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        default: break;
+                    }
+                    kstart = K;
+                }
+            }
             // the common case, over the full chunks (FP64 up to three tiles per wave: the
             // FP64 fragments of four or five would not fit the registers)
             if ((sizeof(T) == 4 || ntu <= 3) && !ta && tb) {
