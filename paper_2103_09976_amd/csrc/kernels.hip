@@ -587,14 +587,15 @@ __device__ __forceinline__ void tall_x_tail(typename Mfma<T>::v4 (&acc)[RW], con
 // operator used as its transpose): a lane's four k of B are a column of B,
 // four separate loads per lane.  Instead each chunk of B (16 k x 16 columns)
 // is read row-wise with one 16-byte load per lane, transposed through the
-// wave's own LDS scratch (16 x 16 floats, an array of its own: no other wave
-// touches it) and read back as one 16-byte LDS read per lane.  FP32, K >= 16; the last partial chunk restarts at K - 16
+// wave's own LDS scratch (16 x 16 elements, an array of its own: no other
+// wave touches it) and read back as one 16-byte (FP64: two) LDS read per
+// lane.  K >= 16; the last partial chunk restarts at K - 16
 // with the rows already summed zeroed in B.  Lanes outside the operand load
 // nothing (B) or element 0 (A, cleared by the later row mask).
-template <int RW, int NT>
-__device__ __forceinline__ void tall_u_rowB(typename Mfma<float>::v4 (&U)[RW], const float* Ap, const float* Bp,
-                                            int lda, int ldb, int K, int wv, int mu, int lr, int lk, int bcol0,
-                                            int ncolv, float alpha, float* scr) {
+template <typename T, int RW, int NT>
+__device__ __forceinline__ void tall_u_rowB(typename Mfma<T>::v4 (&U)[RW], const T* Ap, const T* Bp, int lda,
+                                            int ldb, int K, int wv, int mu, int lr, int lk, int bcol0, int ncolv,
+                                            T alpha, T* scr) {
     constexpr int SL = 16;                      // scratch row stride (16-byte aligned rows)
     const int lane = lr + 16 * lk;
     const int kr = lane >> 2, c4 = 4 * (lane & 3);
@@ -613,7 +614,7 @@ __device__ __forceinline__ void tall_u_rowB(typename Mfma<float>::v4 (&U)[RW], c
         const int k0 = last ? K - 16 : c * 16;
         const int kskip = last ? kfull - k0 : 0;     // rows already summed
         // B rows k0 + kr, columns c4..c4+3 of the slice
-        float bq[4] = {0.f, 0.f, 0.f, 0.f};
+        T bq[4] = {T(0), T(0), T(0), T(0)};
         if (kr >= kskip) {
             const uint32_t o = (uint32_t)((k0 + kr) * ldb + bcol0 + c4);
             if (c4 + 4 <= ncolv) {
@@ -629,22 +630,79 @@ __device__ __forceinline__ void tall_u_rowB(typename Mfma<float>::v4 (&U)[RW], c
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float fb[4];
-        {
+        T fb[4];
+        if constexpr (sizeof(T) == 4) {
             const float4 v = *reinterpret_cast<const float4*>(scr + lr * SL + 4 * lk);
             fb[0] = v.x; fb[1] = v.y; fb[2] = v.z; fb[3] = v.w;
+        } else {
+            const double2 v = *reinterpret_cast<const double2*>(scr + lr * SL + 4 * lk);
+            const double2 u = *reinterpret_cast<const double2*>(scr + lr * SL + 4 * lk + 2);
+            fb[0] = v.x; fb[1] = v.y; fb[2] = u.x; fb[3] = u.y;
         }
-        float fa[NT][4];
+        T fa[NT][4];
 #pragma unroll
         for (int t = 0; t < NT; ++t) ld4_at(Ap, rok[t] ? abase[t] + (uint32_t)(k0 + 4 * lk) : 0u, fa[t]);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) U[t] = Mfma<float>::mma(fa[t][s], fb[s], U[t]);
+            for (int s = 0; s < 4; ++s) U[t] = Mfma<T>::mma(fa[t][s], fb[s], U[t]);
         // every lane's read of this chunk precedes the next chunk's writes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// X . U with X used as its transpose (X[row][k] stored at Xp[k * ldx + row]):
+// a lane's four k of X are four rows of the stored block.  Per chunk of 16 k
+// and output row tile, the 16 x 16 block is read along its stored rows (one
+// 16-byte load per lane), transposed through the wave's LDS scratch and read
+// back as the A fragment.  mu >= 16; the last partial chunk restarts at
+// mu - 16 with the k already summed zeroed in U.
+template <typename T, int RW, int NT, int LD>
+__device__ __forceinline__ void tall_x_transX(typename Mfma<T>::v4 (&acc)[RW], const T* Xp, int ldx, int mu,
+                                              const T* su, int wv, int m, int lr, int lk, T* scr) {
+    constexpr int SL = 16;
+    const int lane = lr + 16 * lk;
+    const int kr = lane >> 2, c4 = 4 * (lane & 3);
+    const int kfull = mu & ~15;
+    const int nch = kfull / 16 + (kfull < mu ? 1 : 0);
+    for (int c = 0; c < nch; ++c) {
+        const bool last = c * 16 >= kfull;
+        const int k0 = last ? mu - 16 : c * 16;
+        const int kskip = last ? kfull - k0 : 0;
+        T ub[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int k = k0 + 4 * lk + s;
+            ub[s] = k >= k0 + kskip ? su[lr * LD + k] : T(0);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int r0 = 16 * (wv + 4 * t);
+            T xq[4] = {T(0), T(0), T(0), T(0)};
+            const uint32_t o = (uint32_t)((k0 + kr) * ldx + r0 + c4);
+            if (r0 + c4 + 4 <= m) {
+                ld4_at(Xp, o, xq);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (r0 + c4 + j < m) xq[j] = ld_at(Xp, o + (uint32_t)j);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) scr[(c4 + j) * SL + kr] = xq[j];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            T xf[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) xf[s] = scr[lr * SL + 4 * lk + s];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[t] = Mfma<T>::mma(xf[s], ub[s], acc[t]);
+        }
     }
 }
 
@@ -668,8 +726,8 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
     constexpr int LD = TallCfg<T>::ld;
     constexpr int NB = TallCfg<T>::nbuf;
     __shared__ __attribute__((aligned(16))) T sU[NB][16 * LD];
-    // per-wave transposition scratch of the row-major B path (FP32 only)
-    __shared__ __attribute__((aligned(16))) float sBt[sizeof(T) == 4 ? 4 * 256 : 4];
+    // per-wave transposition scratch of the row-major B path
+    __shared__ __attribute__((aligned(16))) T sBt[4 * 256];
     __shared__ Group sG[LR ? kRecG : 1];
     __shared__ Contrib sC[LR ? kRecC : 1];
     (void)Bargs;
@@ -750,18 +808,24 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             const bool ta = (ct.flags & F_TRANS_A) != 0, tb = (ct.flags & F_TRANS_B) != 0;
             const int K = ct.k, lda = ct.lda, ldb = ct.ldb;
             int kstart = 0;
-            if constexpr (sizeof(T) == 4) {
-                if (!ta && !tb && K >= 16) {   // B row-major: through the wave's LDS scratch
+            {   // B row-major: through the wave's LDS scratch (FP64 up to three tiles per wave)
+                if (!ta && !tb && K >= 16 && (sizeof(T) == 4 || ntu <= 3)) {
                     const int lr = opaque(lr0), lk = opaque(lk0);
-                    float* scr = sBt + wv * 256;
+                    T* scr = sBt + wv * 256;
                     const int ncolv = min(16, ncv - 16 * w);
                     const int bc0 = tk.col0 + 16 * w;
                     switch (ntu) {
-                        case 1: tall_u_rowB<RW, 1>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
-                        case 2: tall_u_rowB<RW, 2>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
-                        case 3: tall_u_rowB<RW, 3>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
-                        case 4: tall_u_rowB<RW, 4>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
-                        case 5: tall_u_rowB<RW, 5>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        case 1: tall_u_rowB<T, RW, 1>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        case 2: tall_u_rowB<T, RW, 2>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        case 3: tall_u_rowB<T, RW, 3>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr); break;
+                        case 4:
+                            if constexpr (sizeof(T) == 4)
+                                tall_u_rowB<T, RW, 4>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr);
+                            break;
+                        case 5:
+                            if constexpr (sizeof(T) == 4)
+                                tall_u_rowB<T, RW, 5>(U, Ap, Bp, lda, ldb, K, wv, mu, lr, lk, bc0, ncolv, alpha, scr);
+                            break;
                         default: break;
                     }
                     kstart = K;
@@ -893,6 +957,23 @@ __global__ __launch_bounds__(256, (TallCfg<T>::waves)) void tall_kernel(Bases<T>
             const bool tx = (gr.flags & G_TRANS_X) != 0;
             const int ldx = gr.ldx;
             int qstart = 0;
+            if (tx && mu >= 16 && (sizeof(T) == 4 || nto <= 3)) {   // X used as its transpose: through LDS
+                const int lr = opaque(lr0), lk = opaque(lk0);
+                T* scr = sBt + wv * 256;
+                switch (nto) {
+                    case 1: tall_x_transX<T, RW, 1, LD>(acc, Xp, ldx, mu, su, wv, tk.m, lr, lk, scr); break;
+                    case 2: tall_x_transX<T, RW, 2, LD>(acc, Xp, ldx, mu, su, wv, tk.m, lr, lk, scr); break;
+                    case 3: tall_x_transX<T, RW, 3, LD>(acc, Xp, ldx, mu, su, wv, tk.m, lr, lk, scr); break;
+                    case 4:
+                        if constexpr (sizeof(T) == 4) tall_x_transX<T, RW, 4, LD>(acc, Xp, ldx, mu, su, wv, tk.m, lr, lk, scr);
+                        break;
+                    case 5:
+                        if constexpr (sizeof(T) == 4) tall_x_transX<T, RW, 5, LD>(acc, Xp, ldx, mu, su, wv, tk.m, lr, lk, scr);
+                        break;
+                    default: break;
+                }
+                qstart = nru;
+            }
             if ((sizeof(T) == 4 || nto <= 3) && !tx) {   // row-major X over the full 16-row chunks of U
                 const int qfull = mu >> 4;
                 const bool tail = 16 * qfull < mu && mu >= 4;
