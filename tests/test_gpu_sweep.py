@@ -175,3 +175,25 @@ def test_noisy_sweep_stays_variational():
             assert st.energies[0] >= e_fci - 1e-9
         finals.append(got[-1].energies[0])
     assert abs(finals[1] - finals[0]) < 1e-3
+
+
+def test_mixed_precision_sweep_matches_oracle():
+    """The FP32-mixed policy (FP32 products while the residual is large, FP64
+    to finish) inside a sweep: the same energies and kept dimensions as the
+    oracle's exact solves."""
+    d = _lib()
+    from paper_2103_09976_amd import sweep as gsw
+    inp = synth.make_sweep_inputs(7, 6, 0, 8, 7700)
+    start = lambda dim, s, n: synth.random_vectors(dim, n, s)  # noqa: E731
+    seed_of = lambda sw, b, KL: synth.sweep_seed(inp, sw, b, KL)  # noqa: E731
+    ctx = d.Context(1 << 30)
+    try:
+        print("[gpu] mixed-precision sweep K=7 M=8", flush=True)
+        got = gsw.run_sweeps(ctx, inp, 1, 8, start, seed_of, tol=1e-10, precision=d.DMRG_PREC_F32)
+    finally:
+        ctx.close()
+    ref = osw.sweeps(inp, 1, start, M=8, seed_of=seed_of)
+    for g, r in zip(got, ref):
+        np.testing.assert_allclose(g.energies, r.energies, rtol=0, atol=1e-8)
+        assert g.kept == r.kept and g.dims == r.dims
+    assert any(g.davidson.get("matvecs_f32", 0) > 0 for g in got)
