@@ -135,6 +135,25 @@ def cpu_baseline(F_c5: float):
             "extrapolation": "F_alg ratio (workload / sample) times the sample's product time"}
 
 
+def summarize_all_kernels(d: str, top: int = 40):
+    """The top kernels by total time of a rocprofv3 kernel_stats.csv (any run)."""
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        for r in csv.DictReader(open(f)):
+            rows.append((float(r.get("TotalDurationNs", 0)), r))
+    rows.sort(key=lambda x: -x[0])
+    tot = sum(x[0] for x in rows) or 1.0
+    print(f"# all kernels: total {tot / 1e9:.3f} s; top {top} by total time")
+    for t, r in rows[:top]:
+        name = r.get("Name", "").replace("void ", "")
+        i = name.find("(")
+        name = name[:i] if i > 0 else name
+        print(f"{name[:110]}; calls={r.get('Calls')}; total_ms={t / 1e6:.2f}; share={t / tot:.3f}; "
+              f"avg_us={float(r.get('AverageNs', 0)) / 1e3:.1f}")
+
+
 def summarize_profile(d: str):
     """Per-kernel summary of a rocprofv3 CSV output directory of a --profile-apply
     run (kernel_stats.csv: calls and durations; counter_collection.csv:
@@ -229,6 +248,9 @@ def traffic_summary(fetch_dir: str, write_dir: str, cal_bytes: int = 1 << 30):
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profile":
         summarize_profile(sys.argv[2])
+        return
+    if len(sys.argv) == 3 and sys.argv[1] == "--summarize-all-kernels":
+        summarize_all_kernels(sys.argv[2])
         return
     if len(sys.argv) == 4 and sys.argv[1] == "--traffic":
         traffic_summary(sys.argv[2], sys.argv[3])
