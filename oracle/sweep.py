@@ -141,11 +141,14 @@ class Step:
 
 def sweeps(inp, n_sweeps: int, start: Callable[[int, int, int], np.ndarray], M: Optional[int] = None,
            n_roots: int = 1, noise: float = 0.0, noise_vec: Optional[Callable[[int, int], np.ndarray]] = None,
-           tie_rel: float = TIE_REL, seed_of: Optional[Callable[[int, bool, int], int]] = None) -> List[Step]:
+           tie_rel: float = TIE_REL, seed_of: Optional[Callable[[int, bool, int], int]] = None,
+           schedule: Optional[List[Tuple[Optional[int], float]]] = None) -> List[Step]:
     """Two-site sweeps from the starting MPS of ``inp`` (left block of site 0,
     right blocks of 1..K-3 sites).  start(dim, seed, n) gives the start
     vectors, seed_of(sweep, backward, KL) their seed; noise_vec(dim, seed)
-    the perturbations (one per root) when noise != 0.  Returns every step."""
+    the perturbations (one per root) when noise != 0.  schedule: (M, noise)
+    of every sweep (the bond-dimension schedule of a production run), which
+    then sets the sweep count.  Returns every step."""
     K, tgt = inp.K, inp.target
     ints = Integrals(inp.h1e, inp.g2e)
     _, Z = grow_left(vacuum_block(K, True), Site(0, ints), ints, list(range(2, 2 * K)))
@@ -159,7 +162,11 @@ def sweeps(inp, n_sweeps: int, start: Callable[[int, int, int], np.ndarray], M: 
         R[n] = Y
     out: List[Step] = []
     last = K - 3
+    if schedule is not None:
+        n_sweeps = len(schedule)
     for sw in range(n_sweeps):
+        if schedule is not None:
+            M, noise = schedule[sw]
         for backward in (False, True):
             order = range(1, last + 1) if not backward else range(last, 0, -1)
             for KL in order:

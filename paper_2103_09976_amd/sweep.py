@@ -41,7 +41,8 @@ def run_sweeps(ctx: "D.Context", inp, n_sweeps: int, max_states: Optional[int],
                n_roots: int = 1, tol: float = 1e-9, precision: int = D.DMRG_PREC_F64,
                noise: float = 0.0, noise_vec: Optional[Callable[[int, int], np.ndarray]] = None,
                max_iter: int = 500, max_subspace: int = 24, diag_guess: bool = True,
-               on_step: Optional[Callable[[SweepStep], None]] = None) -> List[SweepStep]:
+               on_step: Optional[Callable[[SweepStep], None]] = None,
+               schedule: Optional[List[Tuple[Optional[int], float]]] = None) -> List[SweepStep]:
     """Sweeps from the starting MPS of ``inp`` (integrals, the isometry of
     site 0, random isometries of the right blocks of 1..K-3 sites).
 
@@ -50,7 +51,9 @@ def run_sweeps(ctx: "D.Context", inp, n_sweeps: int, max_states: Optional[int],
     basis state of the j-th lowest diagonal element of H_eff plus 0.1 times
     the seeded vector, else the seeded vector alone.  noise_vec(dim, seed)
     gives one perturbation per root when noise != 0.  max_states None keeps
-    every state with weight.  Returns every step."""
+    every state with weight.  schedule: (max_states, noise) of every sweep
+    (a bond-dimension schedule), which then sets the sweep count.  Returns
+    every step."""
     import time
     import torch
     dev = ctx.device
@@ -63,10 +66,14 @@ def run_sweeps(ctx: "D.Context", inp, n_sweeps: int, max_states: Optional[int],
     for n in range(2, K - 2):
         R[n] = ctx.renormalize(R[n - 1], D.Isometry(inp.right_iso[n - 1], dev))
     last = K - 3
-    M = 0 if max_states is None else int(max_states)
+    if schedule is not None:
+        n_sweeps = len(schedule)
     out: List[SweepStep] = []
     try:
         for sw in range(n_sweeps):
+            if schedule is not None:
+                max_states, noise = schedule[sw]
+            M = 0 if max_states is None else int(max_states)
             for backward in (False, True):
                 order = range(1, last + 1) if not backward else range(last, 0, -1)
                 for KL in order:

@@ -197,3 +197,23 @@ def test_mixed_precision_sweep_matches_oracle():
         np.testing.assert_allclose(g.energies, r.energies, rtol=0, atol=1e-8)
         assert g.kept == r.kept and g.dims == r.dims
     assert any(g.davidson.get("matvecs_f32", 0) > 0 for g in got)
+
+
+def test_bond_dimension_schedule_matches_oracle():
+    d = _lib()
+    from paper_2103_09976_amd import sweep as gsw
+    inp = synth.make_sweep_inputs(7, 6, 0, 8, 7400)
+    start = lambda dim, s, n: synth.random_vectors(dim, n, s)  # noqa: E731
+    seed_of = lambda sw, b, KL: synth.sweep_seed(inp, sw, b, KL)  # noqa: E731
+    sched = [(4, 0.0), (12, 0.0)]
+    ctx = d.Context(1 << 30)
+    try:
+        print("[gpu] schedule sweep K=7 M=4,12", flush=True)
+        got = gsw.run_sweeps(ctx, inp, 0, None, start, seed_of, tol=1e-10, schedule=sched)
+    finally:
+        ctx.close()
+    ref = osw.sweeps(inp, 0, start, seed_of=seed_of, schedule=sched)
+    assert len(got) == len(ref) == 16
+    for g, r in zip(got, ref):
+        np.testing.assert_allclose(g.energies, r.energies, rtol=0, atol=1e-8)
+        assert g.kept == r.kept and g.dims == r.dims

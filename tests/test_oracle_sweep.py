@@ -161,3 +161,18 @@ def test_truncated_sweeps_are_variational_and_improve_with_m():
         finals.append(steps[-1].energies[0])
     assert finals[1] <= finals[0] + 1e-12
     assert finals[1] - e_fci < finals[0] - e_fci
+
+
+def test_schedule_of_bond_dimensions():
+    """A schedule (M = 4, then 12): the first sweep keeps at most M = 4 states
+    (plus multiplet partners), the second grows past them from the blocks the
+    first left, and its last energy lies above FCI and below the first
+    sweep's."""
+    inp = synth.make_sweep_inputs(7, 6, 0, 8, 7400)
+    e_fci = fci.fci_ground_energy(inp.h1e, inp.g2e, 3, 3)
+    steps = osw.sweeps(inp, 0, lambda dim, seed, n: synth.random_vectors(dim, n, seed),
+                       seed_of=lambda sw, b, KL: synth.sweep_seed(inp, sw, b, KL), schedule=[(4, 0.0), (12, 0.0)])
+    assert len(steps) == 16
+    assert all(st.kept <= 4 + 2 for st in steps[:8])
+    assert max(st.kept for st in steps[8:]) > 4
+    assert e_fci - 1e-10 <= steps[-1].energies[0] < steps[7].energies[0]
