@@ -300,7 +300,7 @@ dmrg_status dmrg_renormalize(dmrg_ctx* ctx, const dmrg_opset* in, const dmrg_bsm
  * enlarged left block L' = Lb + d1 (rows in the enlarged order above; pass
  * the result to dmrg_heff_renormalize or dmrg_renormalize of Lb);
  * DMRG_RIGHT: sectors of R' = d2 + Rb (for dmrg_renormalize of Rb).
- *   psi[n_vec * dim] (device, double): the roots, in H's layout; the density
+ *   psi[n_vec * dim] (device, double; n_vec 1..64): the roots, in H's layout; the density
  *     matrix averages them with equal weights, rho_L = sum_k Psi_k Psi_k^T /
  *     n_vec per sector (rho_R: Psi_k^T Psi_k), Psi_k the wavefunction as a
  *     matrix over (L' state, R' state);

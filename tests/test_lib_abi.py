@@ -55,6 +55,11 @@ def test_null_arguments_are_rejected(lib):
     assert lib.dmrg_heff_flops(None) == -1
     assert lib.dmrg_davidson(None, 1, None, None, None, None, None) == -1
     assert lib.dmrg_heff_profile(None, 0, None, None, 0, None, None, None, None) == -1
+    iso = ctypes.c_void_p()
+    assert lib.dmrg_decimate(None, 0, 1, None, 0.0, None, 0, ctypes.byref(iso), None, None) == -1
+    assert lib.dmrg_iso_bsm(None, None) == -1
+    assert lib.dmrg_iso_weights(None, 0, None) == -1
+    lib.dmrg_iso_free(None)
     assert dmrg.DMRG_OK == 0
 
 
