@@ -197,6 +197,8 @@ typedef struct {
  *              one FP32 product of each candidate, then cached for the shape
  *              (the file named by DMRG_TUNE_CACHE, if set, keeps the cache
  *              across processes).  dmrg_heff_get_info reports the choice.
+ *              Without it the list takes the defaults, or DMRG_BALANCE and
+ *              DMRG_TALL_MIN from the environment.
  * DMRG_E_ARG for a layout that does not match the blocks; DMRG_E_WORKSPACE if
  * the arena cannot hold the blocked operators, lists and copies. */
 enum { DMRG_HEFF_GRAPH = 1,      /* products replay a graph of their kernel launches */

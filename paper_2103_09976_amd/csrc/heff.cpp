@@ -335,6 +335,7 @@ static bool g_tune_loaded = false;
 static void lookup_tuning(dmrg_heff* H) {
     H->tune = TuneParams();
     if (const char* e = std::getenv("DMRG_BALANCE")) H->tune.balance = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("DMRG_TALL_MIN")) H->tune.tall_min = std::max(1, std::atoi(e));
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded) {
         g_tune_loaded = true;
@@ -977,7 +978,11 @@ static void drop_graphs(dmrg_heff* H) {
 static dmrg_status autotune(dmrg_heff* H, void* stream) {
     Ctx* C = H->ctx;
     hipStream_t s = (hipStream_t)stream;
-    bool mid = false;   // tiles of 81..96 rows exist, so the tall threshold matters
+    // Two stages: the chunk count first (tall kernel from 97 rows), then, with
+    // the fastest count, the tall kernel from 81 rows if tiles of 81..96 rows
+    // exist.  Lower heights (65, 49) were slower on every workload measured:
+    // the slice kernels serve those tiles better.
+    bool mid = false;
     for (const auto& T : H->base->task)
         for (const dmrgk::Task& t : T) {
             int rows = t.m;
@@ -985,10 +990,7 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
             if (rows > dmrgk::kShortRows && rows <= dmrgk::kMaxRows) mid = true;
         }
     H->cand.clear();
-    for (int bal : {65536, 131072, 262144}) {
-        H->cand.push_back(TuneParams{bal, dmrgk::kMaxRows + 1});
-        if (mid) H->cand.push_back(TuneParams{bal, dmrgk::kShortRows + 1});
-    }
+    H->cand_ms.clear();
     // the current list and its partial tiles make room for the candidates
     free_work(C, H->work);
     if (H->part_region >= 0) C->arena.release(H->part_region);
@@ -999,16 +1001,18 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
     float* x = (float*)(C->arena.base + vreg);
     float* y = x + H->dim;
     if (!C->dry) DMRG_HIP(hipMemsetAsync(x, 0, H->dim * 4 * 2, s));
-    H->cand_ms.assign(H->cand.size(), 0.f);
     hipEvent_t e0, e1;
     DMRG_HIP(hipEventCreate(&e0));
     DMRG_HIP(hipEventCreate(&e1));
     dmrg_status st = DMRG_OK;
     size_t best = 0;
     int64_t biggest = 0;
-    for (size_t k = 0; k < H->cand.size() && st == DMRG_OK; ++k) {
+    TuneParams biggest_tp{};
+    // builds, uploads and (unless dry) times one FP32 product of a candidate
+    auto trial = [&](const TuneParams& tp) {
+        if (st != DMRG_OK) return;
         WorkList w = *H->base;
-        st = finalize_list(H, w, H->cand[k]);
+        st = finalize_list(H, w, tp);
         DevWork dw;
         int64_t preg = -1;
         if (st == DMRG_OK) st = upload_work(C, w, dw, stream);
@@ -1016,7 +1020,12 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
             preg = C->arena.alloc(w.partial_elems * 4);
             if (preg < 0) st = fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's partial tiles");
         }
-        biggest = std::max(biggest, work_bytes(w) + w.partial_elems * 8 * H->n_roots);
+        const int64_t need = work_bytes(w) + w.partial_elems * 8 * H->n_roots;
+        if (need > biggest) {
+            biggest = need;
+            biggest_tp = tp;
+        }
+        float best_ms = 0.f;
         if (st == DMRG_OK && !C->dry) {
             dmrgk::Bases<float> b = bases32(H);
             b.p[dmrgk::kPartialBuf] = preg >= 0 ? (float*)(C->arena.base + preg) : H->f32[0];
@@ -1024,7 +1033,7 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
             b.p[2] = x;
             b.p[3] = y;
             st = run_work_f32(dw, b, 1, stream);   // warm-up
-            float best_ms = 1e30f;
+            best_ms = 1e30f;
             for (int r = 0; r < 2 && st == DMRG_OK; ++r) {
                 hipEventRecord(e0, s);
                 st = run_work_f32(dw, b, 1, stream);
@@ -1034,25 +1043,29 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
                 hipEventElapsedTime(&ms, e0, e1);
                 best_ms = std::min(best_ms, ms);
             }
-            H->cand_ms[k] = best_ms;
-            if (best_ms < H->cand_ms[best]) best = k;
         }
         free_work(C, dw);
         if (preg >= 0) C->arena.release(preg);
+        if (st != DMRG_OK) return;
+        H->cand.push_back(tp);
+        H->cand_ms.push_back(best_ms);
+        if (best_ms < H->cand_ms[best]) best = H->cand.size() - 1;
+    };
+    for (int bal : {65536, 131072, 262144}) trial(TuneParams{bal, dmrgk::kMaxRows + 1});
+    if (mid) {
+        if (C->dry) {
+            // the choice is made on the device: size the rebuild for the largest
+            // of every candidate the second stage could time
+            for (int bal : {65536, 131072, 262144}) trial(TuneParams{bal, dmrgk::kShortRows + 1});
+        } else if (st == DMRG_OK) {
+            trial(TuneParams{H->cand[best].balance, dmrgk::kShortRows + 1});
+        }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     C->arena.release(vreg);
     if (st != DMRG_OK) return st;
-    if (C->dry) {
-        // the choice is made on the device; size the rebuild for the largest candidate
-        for (size_t k = 0; k < H->cand.size(); ++k) {
-            WorkList w = *H->base;
-            finalize_list(H, w, H->cand[k]);
-            if (work_bytes(w) + w.partial_elems * 8 * H->n_roots == biggest) best = k;
-        }
-    }
-    H->tune = H->cand[best];
+    H->tune = C->dry ? biggest_tp : H->cand[best];
     H->tuned = 1;
     WorkList w = *H->base;
     H->base.reset();

@@ -540,6 +540,36 @@ def test_autotune_choice_cache_and_parity(monkeypatch, tmp_path):
     assert cache.read_text().strip()
 
 
+def test_low_tall_threshold_parity(monkeypatch):
+    """Tiles from 49 rows up on the tall kernel (the lowest height the
+    autotuner tries; DMRG_TALL_MIN forces it): 49..96-row tiles take the tall
+    kernel's one- and two-tile-per-wave paths; FP64 and FP32 against the
+    oracle.  At M = 500 the largest sectors have 50 and 83 rows, so the
+    default list runs no tile on the tall kernel."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(14, 14, 0, 500, 82)
+    ref = blockops.MiddleHeff(p, "CN").apply(p.psi)
+    ctx, L, R, H, keep = _step(p, arena=8 << 30)
+    x = torch.from_numpy(p.psi.copy()).cuda()
+    base = H.profile(x, torch.empty_like(x))
+    monkeypatch.setenv("DMRG_TALL_MIN", "49")
+    T = ctx.heff_create(L, R, 1, d.DMRG_PREC_F32)
+    info = T.info()
+    low = T.profile(x, torch.empty_like(x))
+    got = _apply(T, p.psi)
+    got32 = _apply(T, p.psi, d.DMRG_PREC_F32)
+    torch.cuda.synchronize()
+    _close(T, H, L, R, ctx)
+    tall = lambda launches: sum(fl for k, _, fl in launches if 16 <= (k & 255) < 22)  # noqa: E731
+    assert info["tall_min_rows"] == 49
+    assert tall(base) == 0 and tall(low) > 0, (base, low)
+    e64, e32 = _rel(got, ref), _rel(got32, ref)
+    print(f"[gpu] tall_min=49 f64={e64:.2e} f32={e32:.2e}", flush=True)
+    assert e64 <= 1e-12
+    assert e32 <= 1e-5
+
+
 @pytest.mark.parametrize("name", ["C4T", "C5T"])
 def test_contract_shape_twins(name):
     """The two largest workloads' shapes at reduced bond dimension, against the
