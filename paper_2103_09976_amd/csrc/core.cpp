@@ -740,52 +740,82 @@ int64_t work_bytes(const WorkList& w) {
     return std::max<int64_t>(bytes, 256);
 }
 
-dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
+// Copies the selected parts of a list into one arena region: the tasks and
+// reductions (with_tasks) and the groups and contributions (with_records).
+static dmrg_status upload_parts(Ctx* ctx, const WorkList& w, DevWork& d, void* stream, bool with_tasks,
+                                bool with_records) {
+    auto round = [](int64_t x) { return (x + 255) & ~int64_t(255); };
     int64_t bytes = 0;
-    int64_t toff[dmrgk::kNumClass];
-    for (int c = 0; c < dmrgk::kNumClass; ++c) {
-        toff[c] = bytes;
-        bytes += ((int64_t)w.task[c].size() * sizeof(dmrgk::Task) + 255) & ~int64_t(255);
-    }
+    int64_t toff[dmrgk::kNumClass] = {};
+    if (with_tasks)
+        for (int c = 0; c < dmrgk::kNumClass; ++c) {
+            toff[c] = bytes;
+            bytes += round((int64_t)w.task[c].size() * sizeof(dmrgk::Task));
+        }
     const int64_t goff = bytes;
-    bytes += ((int64_t)w.groups.size() * sizeof(dmrgk::Group) + 255) & ~int64_t(255);
+    if (with_records) bytes += round((int64_t)w.groups.size() * sizeof(dmrgk::Group));
     const int64_t coff = bytes;
-    bytes += ((int64_t)w.contribs.size() * sizeof(dmrgk::Contrib) + 255) & ~int64_t(255);
+    if (with_records) bytes += round((int64_t)w.contribs.size() * sizeof(dmrgk::Contrib));
     const int64_t roff = bytes;
-    bytes += ((int64_t)w.reduces.size() * sizeof(dmrgk::Reduce) + 255) & ~int64_t(255);
-    const int64_t reg = ctx->arena.alloc(bytes);
+    if (with_tasks) bytes += round((int64_t)w.reduces.size() * sizeof(dmrgk::Reduce));
+    const int64_t reg = ctx->arena.alloc(std::max<int64_t>(bytes, 256));
     if (reg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for a work list of " + std::to_string(bytes) + " bytes");
     d.region = reg;
     char* base = ctx->arena.base + reg;
     hipStream_t s = (hipStream_t)stream;
     const bool dev = !ctx->dry;
-    for (int c = 0; c < dmrgk::kNumClass; ++c) {
-        d.task[c] = (dmrgk::Task*)(base + toff[c]);
-        d.ntask[c] = (int)w.task[c].size();
-        d.useful[c] = 0;
-        for (const dmrgk::Task& t : w.task[c]) d.useful[c] += task_useful_flops(w, t);
-        if (dev && !w.task[c].empty())
-            DMRG_HIP(hipMemcpyAsync(d.task[c], w.task[c].data(), w.task[c].size() * sizeof(dmrgk::Task),
+    if (with_tasks) {
+        for (int c = 0; c < dmrgk::kNumClass; ++c) {
+            d.task[c] = (dmrgk::Task*)(base + toff[c]);
+            d.ntask[c] = (int)w.task[c].size();
+            d.useful[c] = 0;
+            for (const dmrgk::Task& t : w.task[c]) d.useful[c] += task_useful_flops(w, t);
+            if (dev && !w.task[c].empty())
+                DMRG_HIP(hipMemcpyAsync(d.task[c], w.task[c].data(), w.task[c].size() * sizeof(dmrgk::Task),
+                                        hipMemcpyHostToDevice, s));
+        }
+        d.lds_records = true;
+        for (const auto& T : w.task)
+            for (const dmrgk::Task& t : T) d.lds_records = d.lds_records && records_fit(w, t);
+        d.reduces = (dmrgk::Reduce*)(base + roff);
+        d.nred = (int)w.reduces.size();
+        if (dev && !w.reduces.empty())
+            DMRG_HIP(hipMemcpyAsync(d.reduces, w.reduces.data(), w.reduces.size() * sizeof(dmrgk::Reduce),
                                     hipMemcpyHostToDevice, s));
     }
-    d.groups = (dmrgk::Group*)(base + goff);
-    d.contribs = (dmrgk::Contrib*)(base + coff);
-    if (dev && !w.groups.empty())
-        DMRG_HIP(hipMemcpyAsync(d.groups, w.groups.data(), w.groups.size() * sizeof(dmrgk::Group),
-                                hipMemcpyHostToDevice, s));
-    if (dev && !w.contribs.empty())
-        DMRG_HIP(hipMemcpyAsync(d.contribs, w.contribs.data(), w.contribs.size() * sizeof(dmrgk::Contrib),
-                                hipMemcpyHostToDevice, s));
-    d.lds_records = true;
-    for (const auto& T : w.task)
-        for (const dmrgk::Task& t : T) d.lds_records = d.lds_records && records_fit(w, t);
-    d.reduces = (dmrgk::Reduce*)(base + roff);
-    d.nred = (int)w.reduces.size();
-    if (dev && !w.reduces.empty())
-        DMRG_HIP(hipMemcpyAsync(d.reduces, w.reduces.data(), w.reduces.size() * sizeof(dmrgk::Reduce),
-                                hipMemcpyHostToDevice, s));
+    if (with_records) {
+        d.groups = (dmrgk::Group*)(base + goff);
+        d.contribs = (dmrgk::Contrib*)(base + coff);
+        if (dev && !w.groups.empty())
+            DMRG_HIP(hipMemcpyAsync(d.groups, w.groups.data(), w.groups.size() * sizeof(dmrgk::Group),
+                                    hipMemcpyHostToDevice, s));
+        if (dev && !w.contribs.empty())
+            DMRG_HIP(hipMemcpyAsync(d.contribs, w.contribs.data(), w.contribs.size() * sizeof(dmrgk::Contrib),
+                                    hipMemcpyHostToDevice, s));
+    }
     if (dev) DMRG_HIP(hipStreamSynchronize(s));   // host vectors may be released after return
     return DMRG_OK;
+}
+
+dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
+    return upload_parts(ctx, w, d, stream, true, true);
+}
+
+dmrg_status upload_records(Ctx* ctx, const WorkList& w, DevWork& d, void* stream) {
+    return upload_parts(ctx, w, d, stream, false, true);
+}
+
+dmrg_status upload_tasks(Ctx* ctx, const WorkList& w, const DevWork& recs, DevWork& d, void* stream) {
+    const dmrg_status st = upload_parts(ctx, w, d, stream, true, false);
+    d.groups = recs.groups;
+    d.contribs = recs.contribs;
+    return st;
+}
+
+int64_t task_bytes(const WorkList& w) {
+    int64_t bytes = 0;
+    for (const auto& T : w.task) bytes += ((int64_t)T.size() * sizeof(dmrgk::Task) + 255) & ~int64_t(255);
+    return bytes + (((int64_t)w.reduces.size() * sizeof(dmrgk::Reduce) + 255) & ~int64_t(255));
 }
 
 void free_work(Ctx* ctx, DevWork& d) {

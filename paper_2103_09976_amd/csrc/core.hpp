@@ -252,6 +252,12 @@ struct DevWork {
     double useful[dmrgk::kNumClass] = {};   // useful MFMA flops per class (one vector)
 };
 dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
+// the groups and contributions alone, and the tasks and reductions alone (their
+// groups and contributions those of recs: lists that differ only in their tasks
+// share one copy of the records)
+dmrg_status upload_records(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
+dmrg_status upload_tasks(Ctx* ctx, const WorkList& w, const DevWork& recs, DevWork& d, void* stream);
+int64_t task_bytes(const WorkList& w);   // arena bytes upload_tasks takes
 // arena bytes upload_work takes for a list
 int64_t work_bytes(const WorkList& w);
 // splits tiles above kMaxRows rows, then checks every operand of every task on the

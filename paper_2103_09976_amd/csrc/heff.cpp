@@ -88,6 +88,7 @@ struct dmrg_heff {
     int64_t dim = 0;
     int n_roots = 1;
     DevWork work;
+    DevWork recs;   // groups and contributions of work when held apart (autotuned lists)
     // diagonal
     int64_t diag_region = -1;
     dmrgk::DiagBlock* dblocks = nullptr;
@@ -535,13 +536,21 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         WorkList wl;
         std::vector<dmrgk::DiagBlock> dbl;
         std::vector<dmrgk::DiagTerm> dtm;
-        std::unordered_map<int64_t, int64_t> ops;
+        std::vector<std::pair<int64_t, int64_t>> ops;   // (operator block key, elements)
+        std::vector<std::vector<std::pair<int64_t, int64_t>>> opshard;   // ops by key hash, sorted, unique
         std::vector<double> lfx, lfy, rfx, rfy;
+    };
+    const size_t nblk = H->blocks.size();
+    unsigned nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (nblk < 64) nth = 1;
+    const unsigned nshard = nth;
+    auto shard_of = [nshard](int64_t key) {
+        return (unsigned)(((uint64_t)key * 0x9E3779B97F4A7C15ull >> 40) % nshard);
     };
     auto work = [&](size_t o0, size_t o1, Local& Lc) {
         Lc.lfx.assign(NT, 0.0); Lc.lfy.assign(NT, 0.0); Lc.rfx.assign(NT, 0.0); Lc.rfy.assign(NT, 0.0);
         WorkList& wl = Lc.wl;
-        auto note = [&](int buf, int64_t o, int64_t n) { Lc.ops[((int64_t)buf << 56) ^ o] = n; };
+        auto note = [&](int buf, int64_t o, int64_t n) { Lc.ops.emplace_back(((int64_t)buf << 56) ^ o, n); };
         for (size_t o = o0; o < o1; ++o) {
             const PsiBlock& O = H->blocks[o];
             const int g0 = (int)wl.groups.size();
@@ -692,10 +701,15 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
             Lc.dbl.push_back(db);
             emit_block_tasks(wl, 3, O.off, O.mb, O.ma, O.mb, g0, (int)wl.groups.size());
         }
+        // a key names one block of one operator, so its size is the same wherever
+        // noted; the distinct keys go to the shards the merge counts them in
+        std::sort(Lc.ops.begin(), Lc.ops.end());
+        Lc.opshard.assign(nshard, {});
+        for (size_t j = 0; j < Lc.ops.size(); ++j)
+            if (j == 0 || Lc.ops[j].first != Lc.ops[j - 1].first)
+                Lc.opshard[shard_of(Lc.ops[j].first)].push_back(Lc.ops[j]);
+        std::vector<std::pair<int64_t, int64_t>>().swap(Lc.ops);
     };
-    const size_t nblk = H->blocks.size();
-    unsigned nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-    if (nblk < 64) nth = 1;
     std::vector<Local> loc(nth);
     {
         // interleaved chunks balance the uneven cost of output blocks
@@ -719,26 +733,98 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         for (size_t kk = 0; kk < k; ++kk) ordered.push_back(std::move(parts[kk % nth][pos[kk % nth]++]));
         loc.swap(ordered);
     }
+    clk.mark("work list: blocks");
+    // Merge the chunks in output-block order: prefix offsets first, then the
+    // copies (with group / contribution / diagonal-term indices shifted) run
+    // on the worker threads, each on its own chunks.
     WorkList wl;
     std::vector<dmrgk::DiagBlock> dbl;
     std::vector<dmrgk::DiagTerm> dtm;
-    std::unordered_map<int64_t, int64_t> opsz;
     std::vector<double> lfx(NT, 0.0), lfy(NT, 0.0), rfx(NT, 0.0), rfy(NT, 0.0);
-    for (Local& Lc : loc) {
-        const int goff = (int)wl.groups.size(), coff = (int)wl.contribs.size(), doff = (int)dtm.size();
-        for (int c = 0; c < dmrgk::kNumClass; ++c)
-            for (dmrgk::Task t : Lc.wl.task[c]) { t.g0 += goff; t.g1 += goff; wl.task[c].push_back(t); }
-        for (dmrgk::Group g : Lc.wl.groups) { g.c0 += coff; g.c1 += coff; wl.groups.push_back(g); }
-        wl.contribs.insert(wl.contribs.end(), Lc.wl.contribs.begin(), Lc.wl.contribs.end());
-        for (dmrgk::DiagBlock d : Lc.dbl) { d.c0 += doff; d.c1 += doff; dbl.push_back(d); }
-        dtm.insert(dtm.end(), Lc.dtm.begin(), Lc.dtm.end());
-        for (auto& kv : Lc.ops) opsz[kv.first] = kv.second;
-        for (size_t t = 0; t < NT; ++t) { lfx[t] += Lc.lfx[t]; lfy[t] += Lc.lfy[t]; rfx[t] += Lc.rfx[t]; rfy[t] += Lc.rfy[t]; }
-        Lc = Local();
-    }
     int64_t op_bytes = 0;
-    for (auto& kv : opsz) op_bytes += kv.second;
-    clk.mark("work list");
+    {
+        const size_t nl = loc.size();
+        std::vector<size_t> go(nl + 1, 0), co(nl + 1, 0), bo(nl + 1, 0), to(nl + 1, 0);
+        std::vector<size_t> ko((nl + 1) * dmrgk::kNumClass, 0);
+        for (size_t i = 0; i < nl; ++i) {
+            const Local& Lc = loc[i];
+            go[i + 1] = go[i] + Lc.wl.groups.size();
+            co[i + 1] = co[i] + Lc.wl.contribs.size();
+            bo[i + 1] = bo[i] + Lc.dbl.size();
+            to[i + 1] = to[i] + Lc.dtm.size();
+            for (int c = 0; c < dmrgk::kNumClass; ++c)
+                ko[(i + 1) * dmrgk::kNumClass + c] = ko[i * dmrgk::kNumClass + c] + Lc.wl.task[c].size();
+            for (size_t t = 0; t < NT; ++t) {
+                lfx[t] += Lc.lfx[t];
+                lfy[t] += Lc.lfy[t];
+                rfx[t] += Lc.rfx[t];
+                rfy[t] += Lc.rfy[t];
+            }
+        }
+        if (co[nl] > (size_t)INT32_MAX || go[nl] > (size_t)INT32_MAX || to[nl] > (size_t)INT32_MAX)
+            return fail(DMRG_E_UNSUPPORTED, "work list beyond 2^31 groups or contributions");
+        wl.groups.resize(go[nl]);
+        wl.contribs.resize(co[nl]);
+        dbl.resize(bo[nl]);
+        dtm.resize(to[nl]);
+        for (int c = 0; c < dmrgk::kNumClass; ++c) wl.task[c].resize(ko[nl * dmrgk::kNumClass + c]);
+        const unsigned nw = std::max(1u, std::min<unsigned>(nth, (unsigned)nl));
+        auto copy_part = [&](unsigned w) {
+            for (size_t i = w; i < nl; i += nw) {
+                const Local& Lc = loc[i];
+                const int goff = (int)go[i], coff = (int)co[i], doff = (int)to[i];
+                for (int c = 0; c < dmrgk::kNumClass; ++c) {
+                    dmrgk::Task* d = wl.task[c].data() + ko[i * dmrgk::kNumClass + c];
+                    for (dmrgk::Task t : Lc.wl.task[c]) {
+                        t.g0 += goff;
+                        t.g1 += goff;
+                        *d++ = t;
+                    }
+                }
+                dmrgk::Group* dg = wl.groups.data() + go[i];
+                for (dmrgk::Group g : Lc.wl.groups) {
+                    g.c0 += coff;
+                    g.c1 += coff;
+                    *dg++ = g;
+                }
+                std::copy(Lc.wl.contribs.begin(), Lc.wl.contribs.end(), wl.contribs.begin() + co[i]);
+                dmrgk::DiagBlock* db = dbl.data() + bo[i];
+                for (dmrgk::DiagBlock x : Lc.dbl) {
+                    x.c0 += doff;
+                    x.c1 += doff;
+                    *db++ = x;
+                }
+                std::copy(Lc.dtm.begin(), Lc.dtm.end(), dtm.begin() + to[i]);
+            }
+        };
+        // bytes of the distinct operator blocks: each shard of keys gathered
+        // from every chunk, sorted and deduplicated on a thread of its own
+        std::vector<int64_t> shard_bytes(nshard, 0);
+        auto count_shard = [&](unsigned sh) {
+            std::vector<std::pair<int64_t, int64_t>> mine;
+            size_t n = 0;
+            for (const Local& Lc : loc) n += Lc.opshard[sh].size();
+            mine.reserve(n);
+            for (const Local& Lc : loc) mine.insert(mine.end(), Lc.opshard[sh].begin(), Lc.opshard[sh].end());
+            std::sort(mine.begin(), mine.end());
+            int64_t sum = 0;
+            for (size_t j = 0; j < mine.size(); ++j)
+                if (j == 0 || mine[j].first != mine[j - 1].first) sum += mine[j].second;
+            shard_bytes[sh] = sum;
+        };
+        auto run = [&](unsigned n, auto&& f) {
+            std::vector<std::thread> th;
+            for (unsigned w = 0; w < n; ++w) th.emplace_back([&, w]() { f(w); });
+            for (auto& x : th) x.join();
+        };
+        run(nw, copy_part);
+        run(nshard, count_shard);
+        for (int64_t b : shard_bytes) op_bytes += b;
+        run(nw, [&](unsigned w) {
+            for (size_t i = w; i < nl; i += nw) loc[i] = Local();
+        });
+    }
+    clk.mark("work list: merge");
     std::vector<double> lf(NT), rf(NT);
     for (size_t t = 0; t < NT; ++t) {
         lf[t] = lfx[t] + lfy[t];
@@ -761,10 +847,19 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         sz[6] = H->TML.elems;
         sz[7] = H->TMR.elems;
         for (int i = 0; i < dmrgk::kMaxBuf; ++i) H->buf_elems[i] = sz[i];
-        if (H->flags & DMRG_HEFF_AUTOTUNE) H->base.reset(new WorkList(wl));
         lookup_tuning(H);
-        dmrg_status vs = finalize_list(H, wl, H->tune);
-        if (vs != DMRG_OK) return vs;
+        if ((H->flags & DMRG_HEFF_AUTOTUNE) && H->tuned == 0) {
+            // the candidates differ only in their tasks: tiles above kTallRows are
+            // split here, once, and the tuner shares the groups and contributions
+            wl.tall_min = H->tune.tall_min;
+            reclassify(wl);
+            split_large(wl);
+            H->base.reset(new WorkList(std::move(wl)));
+            wl = WorkList();
+        } else {
+            dmrg_status vs = finalize_list(H, wl, H->tune);
+            if (vs != DMRG_OK) return vs;
+        }
         for (const auto& d : dtm) {
             if (d.x_off >= 0 && (d.xbuf < 0 || d.xbuf >= 8 || d.x_off >= sz[d.xbuf])) return fail(DMRG_E_STATE, "diag X");
             if (d.y_off >= 0 && (d.ybuf < 0 || d.ybuf >= 8 || d.y_off >= sz[d.ybuf])) return fail(DMRG_E_STATE, "diag Y");
@@ -814,14 +909,16 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
         std::fprintf(stderr, "[dmrg] tasks %zu groups %zu contribs %zu reductions %zu partial %.1f MB diag terms %zu\n",
                      wl.ntasks(), wl.groups.size(), wl.contribs.size(), wl.reduces.size(),
                      wl.partial_elems * 8.0 * H->n_roots / 1e6, dtm.size());
-    H->part_elems = wl.partial_elems;
-    if (H->part_elems > 0) {
-        H->part_region = C->arena.alloc(H->part_elems * 8 * H->n_roots);
-        if (H->part_region < 0) return fail(DMRG_E_WORKSPACE, "arena too small for partial tiles");
-        H->part = C->arena.base + H->part_region;
+    if (!H->base) {   // an autotuned list is uploaded by the tuner
+        H->part_elems = wl.partial_elems;
+        if (H->part_elems > 0) {
+            H->part_region = C->arena.alloc(H->part_elems * 8 * H->n_roots);
+            if (H->part_region < 0) return fail(DMRG_E_WORKSPACE, "arena too small for partial tiles");
+            H->part = C->arena.base + H->part_region;
+        }
+        dmrg_status st = upload_work(C, wl, H->work, stream);
+        if (st != DMRG_OK) return st;
     }
-    dmrg_status st = upload_work(C, wl, H->work, stream);
-    if (st != DMRG_OK) return st;
     clk.mark("upload");
     // diagonal lists
     {
@@ -839,6 +936,7 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
                 DMRG_HIP(hipMemcpy(H->dterms, dtm.data(), dtm.size() * sizeof(dmrgk::DiagTerm), hipMemcpyHostToDevice));
         }
     }
+    clk.mark("diagonal lists");
     return DMRG_OK;
 }
 
@@ -991,11 +1089,11 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
         }
     H->cand.clear();
     H->cand_ms.clear();
-    // the current list and its partial tiles make room for the candidates
-    free_work(C, H->work);
-    if (H->part_region >= 0) C->arena.release(H->part_region);
-    H->part_region = -1;
-    H->part = nullptr;
+    WorkList& base = *H->base;
+    // every candidate's tasks index the same groups and contributions: one copy
+    // on the device, held by H from here on (released with it on any failure)
+    dmrg_status st = upload_records(C, base, H->recs, stream);
+    if (st != DMRG_OK) return st;
     const int64_t vreg = C->arena.alloc(H->dim * 4 * 2);
     if (vreg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's vectors");
     float* x = (float*)(C->arena.base + vreg);
@@ -1004,48 +1102,61 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
     hipEvent_t e0, e1;
     DMRG_HIP(hipEventCreate(&e0));
     DMRG_HIP(hipEventCreate(&e1));
-    dmrg_status st = DMRG_OK;
     size_t best = 0;
     int64_t biggest = 0;
     TuneParams biggest_tp{};
-    // builds, uploads and (unless dry) times one FP32 product of a candidate
+    // a candidate's list: the base's tasks, with its groups and contributions
+    // lent (moved, not copied) for the time of the call
+    auto with_list = [&](const TuneParams& tp, auto&& use) {
+        WorkList w;
+        for (int c = 0; c < dmrgk::kNumClass; ++c) w.task[c] = base.task[c];
+        w.groups.swap(base.groups);
+        w.contribs.swap(base.contribs);
+        dmrg_status r = finalize_list(H, w, tp);
+        if (r == DMRG_OK) r = use(w);
+        base.groups.swap(w.groups);
+        base.contribs.swap(w.contribs);
+        return r;
+    };
+    // uploads and (unless dry) times one FP32 product of a candidate
     auto trial = [&](const TuneParams& tp) {
         if (st != DMRG_OK) return;
-        WorkList w = *H->base;
-        st = finalize_list(H, w, tp);
-        DevWork dw;
-        int64_t preg = -1;
-        if (st == DMRG_OK) st = upload_work(C, w, dw, stream);
-        if (st == DMRG_OK && w.partial_elems > 0) {
-            preg = C->arena.alloc(w.partial_elems * 4);
-            if (preg < 0) st = fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's partial tiles");
-        }
-        const int64_t need = work_bytes(w) + w.partial_elems * 8 * H->n_roots;
-        if (need > biggest) {
-            biggest = need;
-            biggest_tp = tp;
-        }
         float best_ms = 0.f;
-        if (st == DMRG_OK && !C->dry) {
-            dmrgk::Bases<float> b = bases32(H);
-            b.p[dmrgk::kPartialBuf] = preg >= 0 ? (float*)(C->arena.base + preg) : H->f32[0];
-            b.vstride[dmrgk::kPartialBuf] = w.partial_elems;
-            b.p[2] = x;
-            b.p[3] = y;
-            st = run_work_f32(dw, b, 1, stream);   // warm-up
-            best_ms = 1e30f;
-            for (int r = 0; r < 2 && st == DMRG_OK; ++r) {
-                hipEventRecord(e0, s);
-                st = run_work_f32(dw, b, 1, stream);
-                hipEventRecord(e1, s);
-                if (st == DMRG_OK && hipEventSynchronize(e1) != hipSuccess) st = fail(DMRG_E_HIP, "autotune timing");
-                float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
-                best_ms = std::min(best_ms, ms);
+        st = with_list(tp, [&](const WorkList& w) -> dmrg_status {
+            DevWork dw;
+            int64_t preg = -1;
+            dmrg_status r = upload_tasks(C, w, H->recs, dw, stream);
+            if (r == DMRG_OK && w.partial_elems > 0) {
+                preg = C->arena.alloc(w.partial_elems * 4);
+                if (preg < 0) r = fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's partial tiles");
             }
-        }
-        free_work(C, dw);
-        if (preg >= 0) C->arena.release(preg);
+            const int64_t need = task_bytes(w) + w.partial_elems * 8 * H->n_roots;
+            if (need > biggest) {
+                biggest = need;
+                biggest_tp = tp;
+            }
+            if (r == DMRG_OK && !C->dry) {
+                dmrgk::Bases<float> b = bases32(H);
+                b.p[dmrgk::kPartialBuf] = preg >= 0 ? (float*)(C->arena.base + preg) : H->f32[0];
+                b.vstride[dmrgk::kPartialBuf] = w.partial_elems;
+                b.p[2] = x;
+                b.p[3] = y;
+                r = run_work_f32(dw, b, 1, stream);   // warm-up
+                best_ms = 1e30f;
+                for (int k = 0; k < 2 && r == DMRG_OK; ++k) {
+                    hipEventRecord(e0, s);
+                    r = run_work_f32(dw, b, 1, stream);
+                    hipEventRecord(e1, s);
+                    if (r == DMRG_OK && hipEventSynchronize(e1) != hipSuccess) r = fail(DMRG_E_HIP, "autotune timing");
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    best_ms = std::min(best_ms, ms);
+                }
+            }
+            free_work(C, dw);
+            if (preg >= 0) C->arena.release(preg);
+            return r;
+        });
         if (st != DMRG_OK) return;
         H->cand.push_back(tp);
         H->cand_ms.push_back(best_ms);
@@ -1067,7 +1178,11 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
     if (st != DMRG_OK) return st;
     H->tune = C->dry ? biggest_tp : H->cand[best];
     H->tuned = 1;
-    WorkList w = *H->base;
+    // the chosen list: the base's records themselves (no copy), then the base goes
+    WorkList w;
+    for (int c = 0; c < dmrgk::kNumClass; ++c) w.task[c].swap(base.task[c]);
+    w.groups.swap(base.groups);
+    w.contribs.swap(base.contribs);
     H->base.reset();
     st = finalize_list(H, w, H->tune);
     if (st != DMRG_OK) return st;
@@ -1077,7 +1192,7 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
         if (H->part_region < 0) return fail(DMRG_E_WORKSPACE, "arena too small for partial tiles");
         H->part = C->arena.base + H->part_region;
     }
-    st = upload_work(C, w, H->work, stream);
+    st = upload_tasks(C, w, H->recs, H->work, stream);
     if (st == DMRG_OK && !C->dry) store_tuning(H);
     return st;
 }
@@ -1126,13 +1241,17 @@ dmrg_status dmrg_heff_create(dmrg_ctx* ctx, const dmrg_opset* left, const dmrg_o
     H->flags = flags;
     st = build_heff(H, stream);
     H->layout = nullptr;
+    PhaseClock clk;
     if (st == DMRG_OK && precision == DMRG_PREC_F32) st = ensure_f32(H, stream);
+    clk.mark("FP32 copies");
     if (st == DMRG_OK && H->base && H->tuned == 0) st = autotune(H, stream);
+    clk.mark("autotune");
     H->base.reset();
     if (st == DMRG_OK && !ctx->dry) {
         const int e = (int)hipStreamSynchronize((hipStream_t)stream);
         if (e) st = hip_fail(e, "heff create");
     }
+    clk.mark("create: synchronize");
     if (st != DMRG_OK) {
         dmrg_heff_free(H);
         return st;
@@ -1321,6 +1440,7 @@ void dmrg_heff_free(dmrg_heff* H) {
     Ctx* C = H->ctx;
     drop_graphs(H);
     free_work(C, H->work);
+    free_work(C, H->recs);
     free_set(C, H->TL);
     free_set(C, H->TR);
     free_set(C, H->TML);
