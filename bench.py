@@ -271,9 +271,17 @@ def main():
     ap.add_argument("--sweep", type=int, default=0,
                     help="instead: this many two-site sweeps over the whole chain of the workload's shape "
                          "(K, N, S_z, M; FP32-mixed Davidson to residual 1e-6), one JSON line of per-step times")
+    ap.add_argument("--sweep-schedule", default="",
+                    help="with --sweep: bond dimension and noise of every sweep, 'M:noise,M:noise,...' "
+                         "(sets the sweep count)")
     args = ap.parse_args()
+    if args.sweep_schedule:
+        args.schedule = [(int(m), float(n)) for m, n in (x.split(":") for x in args.sweep_schedule.split(","))]
+        args.sweep = len(args.schedule)
+    else:
+        args.schedule = None
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the multi-GPU (sub-Hamiltonian) path is not part of this build",
+        print("bench.py runs on one GPU only: the multi-GPU (sub-Hamiltonian) path is not implemented",
               file=sys.stderr)
         sys.exit(2)
     if args.sweep:
@@ -521,7 +529,8 @@ def sweep_bench(args):
     t0 = time.perf_counter()
     gsw.run_sweeps(ctx, inp, args.sweep, kw["M"], lambda d, s, n: synth.random_vectors(d, n, s),
                    lambda sw, b, KL: synth.sweep_seed(inp, sw, b, KL), tol=1e-6, precision=dmrg.DMRG_PREC_F32,
-                   max_iter=300, on_step=on_step)
+                   max_iter=300, on_step=on_step, schedule=args.schedule,
+                   noise_vec=lambda d, s: synth.random_vectors(d, 1, s)[0])
     wall = time.perf_counter() - t0
     ctx.close()
     tot = {k: round(sum(r.ms.get(k, 0.0) for r in rows), 1) for k in ("heff_create", "davidson", "decimate",
@@ -529,7 +538,11 @@ def sweep_bench(args):
     print(json.dumps({
         "mode": "sweep", "workload": f"{args.workload} shape, whole chain: K={kw['K']}, N={kw['n_elec']}, "
                                      f"2S_z={kw['two_sz']}, M={kw['M']}",
-        "sweeps": args.sweep, "steps": len(rows), "wall_s": round(wall, 2), "ms_totals": tot,
+        "sweeps": args.sweep, "schedule": args.schedule, "steps": len(rows), "wall_s": round(wall, 2),
+        "ms_totals": tot,
+        # energy at the end of every sweep (its last step), and the change over the last sweep
+        "energy_per_sweep": [[r.energies[0] for r in rows if r.sweep == k][-1] for k in range(args.sweep)
+                             if any(r.sweep == k for r in rows)],
         "energies_last_half_sweep": [r.energies[0] for r in rows if r.sweep == args.sweep - 1 and r.backward],
         "final_energy": rows[-1].energies[0] if rows else None,
         "max_trunc_err_last_sweep": max((r.trunc_err for r in rows if r.sweep == args.sweep - 1), default=None),
