@@ -542,6 +542,7 @@ static dmrg_status build_heff(dmrg_heff* H, void* stream) {
     };
     const size_t nblk = H->blocks.size();
     unsigned nth = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if (const char* e = std::getenv("DMRG_HOST_THREADS")) nth = (unsigned)std::max(1, std::min(32, std::atoi(e)));
     if (nblk < 64) nth = 1;
     const unsigned nshard = nth;
     auto shard_of = [nshard](int64_t key) {

@@ -570,6 +570,30 @@ def test_low_tall_threshold_parity(monkeypatch):
     assert e32 <= 1e-5
 
 
+def test_work_list_independent_of_host_threads(monkeypatch):
+    """The work list is built on several host threads and merged in output-block
+    order: one thread and the default count give the same list (tasks,
+    reductions, partial tiles, algorithmic flops and bytes) and bitwise-equal
+    products in both precisions."""
+    import torch
+    d = _lib()
+    p = synth.make_problem(12, 12, 0, None, 81)
+    ctx, L, R, H, keep = _step(p, arena=8 << 30)
+    monkeypatch.setenv("DMRG_HOST_THREADS", "1")
+    H1 = ctx.heff_create(L, R, 1, d.DMRG_PREC_F32)
+    monkeypatch.delenv("DMRG_HOST_THREADS")
+    try:
+        i0, i1 = H.info(), H1.info()
+        for k in ("tasks", "reductions", "partial_elems", "balance_target", "tall_min_rows"):
+            assert i0[k] == i1[k], k
+        assert H.flops == H1.flops and H.bytes(d.DMRG_PREC_F64) == H1.bytes(d.DMRG_PREC_F64)
+        for prec in (d.DMRG_PREC_F64, d.DMRG_PREC_F32):
+            a, b = _apply(H, p.psi, prec), _apply(H1, p.psi, prec)
+            assert np.array_equal(a, b), prec
+    finally:
+        _close(H1, H, L, R, ctx)
+
+
 @pytest.mark.parametrize("name", ["C4T", "C5T"])
 def test_contract_shape_twins(name):
     """The two largest workloads' shapes at reduced bond dimension, against the
