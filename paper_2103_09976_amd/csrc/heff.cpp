@@ -1119,17 +1119,27 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
         base.contribs.swap(w.contribs);
         return r;
     };
+    float margin = 1.f;   // a candidate is kept if faster than margin x the best so far
     // uploads and (unless dry) times one FP32 product of a candidate
     auto trial = [&](const TuneParams& tp) {
         if (st != DMRG_OK) return;
         float best_ms = 0.f;
+        bool skipped = false;
         st = with_list(tp, [&](const WorkList& w) -> dmrg_status {
             DevWork dw;
             int64_t preg = -1;
             dmrg_status r = upload_tasks(C, w, H->recs, dw, stream);
+            // the partial tiles at the size the chosen list takes (8-byte
+            // elements, n_roots vectors): a candidate that does not fit is
+            // skipped, unless none has fitted yet
             if (r == DMRG_OK && w.partial_elems > 0) {
-                preg = C->arena.alloc(w.partial_elems * 4);
-                if (preg < 0) r = fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's partial tiles");
+                preg = C->arena.alloc(w.partial_elems * 8 * H->n_roots);
+                if (preg < 0) {
+                    free_work(C, dw);
+                    if (H->cand.empty()) return fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's partial tiles");
+                    skipped = true;
+                    return DMRG_OK;
+                }
             }
             const int64_t need = task_bytes(w) + w.partial_elems * 8 * H->n_roots;
             if (need > biggest) {
@@ -1142,9 +1152,8 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
                 b.vstride[dmrgk::kPartialBuf] = w.partial_elems;
                 b.p[2] = x;
                 b.p[3] = y;
-                // a warm-up, then the best of two timed runs, or of one when the
-                // warm-up took over 100 ms (run-to-run spread is then well
-                // below the candidates' differences)
+                // a warm-up, then the best of two timed runs (one when the
+                // warm-up took over 100 ms)
                 best_ms = 1e30f;
                 int runs = 2;
                 for (int k = -1; k < runs && r == DMRG_OK; ++k) {
@@ -1165,17 +1174,21 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
             if (preg >= 0) C->arena.release(preg);
             return r;
         });
-        if (st != DMRG_OK) return;
+        if (st != DMRG_OK || skipped) return;
         H->cand.push_back(tp);
         H->cand_ms.push_back(best_ms);
-        if (best_ms < H->cand_ms[best]) best = H->cand.size() - 1;
+        if (best_ms < H->cand_ms[best] * margin) best = H->cand.size() - 1;
     };
-    for (int bal : {65536, 131072, 262144}) trial(TuneParams{bal, dmrgk::kMaxRows + 1});
+    const int kBalances[] = {65536, 131072, 262144, 524288};
+    for (int bal : kBalances) trial(TuneParams{bal, dmrgk::kMaxRows + 1});
+    // the lower threshold must win by more than 0.5 % (a tie keeps the first
+    // stage's list, so the choice does not flip on timing noise)
+    margin = 0.995f;
     if (mid) {
         if (C->dry) {
             // the choice is made on the device: size the rebuild for the largest
             // of every candidate the second stage could time
-            for (int bal : {65536, 131072, 262144}) trial(TuneParams{bal, dmrgk::kShortRows + 1});
+            for (int bal : kBalances) trial(TuneParams{bal, dmrgk::kShortRows + 1});
         } else if (st == DMRG_OK) {
             trial(TuneParams{H->cand[best].balance, dmrgk::kShortRows + 1});
         }
