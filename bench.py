@@ -25,6 +25,7 @@ import os
 import platform
 import sys
 import time
+from typing import Optional
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -60,11 +61,13 @@ def launch_kernel_name(kind: int, prec: str = "float") -> str:
     return f"reduce_kernel<{prec}>"
 
 
-def counted_traffic(workload: str, kernel: str):
+def counted_traffic(workload: str, kernel: str, heff_info: Optional[dict] = None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel calibration), or None when
-    the summary is missing or was taken on another version of the kernel source."""
+    the summary is missing, was taken on another version of the kernel source, or
+    on a work list of another chunk count or tall threshold than heff_info's."""
     import hashlib
+    import re
     path = os.path.join(PROFILES, f"hbm_traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -72,6 +75,11 @@ def counted_traffic(workload: str, kernel: str):
     lines = open(path).read().splitlines()
     if not any(l.strip() == f"kernels.hip sha256: {sha}" for l in lines):
         return None
+    if heff_info is not None:
+        m = re.search(r"DMRG_BALANCE=(\d+), tall from (\d+) rows", "\n".join(lines))
+        if not m or (int(m.group(1)), int(m.group(2))) != (heff_info.get("balance_target"),
+                                                            heff_info.get("tall_min_rows")):
+            return None
     for l in lines:
         if l.startswith("kernel: ") and f"name={kernel};" in l:
             for f in l.split(";"):
@@ -491,7 +499,7 @@ def main():
         "arena_peak_gb": round(ctx.arena_peak / 2**30, 2),
         "terms_2idx_1idx_H": H.terms(),
         "heff": H.info(),
-        "roofline": roofline(launches, F, args.workload),
+        "roofline": roofline(launches, F, args.workload, H.info()),
         "launches_f32": [{"kernel": launch_kernel_name(k), "ms": round(ms, 3), "useful_tflop": round(fl / 1e12, 4)}
                          for k, ms, fl in launches if ms > 0],
     }
@@ -552,7 +560,7 @@ def sweep_bench(args):
     }), flush=True)
 
 
-def roofline(launches, F, workload):
+def roofline(launches, F, workload, heff_info=None):
     """Roofline of the dominant kernel (the longest launch of one FP32 H_eff product,
     timed live with HIP events on the launch stream).  Its algorithmic flops are its
     share of F_alg: the useful MFMA flops of its tiles, scaled so that the shares of all
@@ -563,7 +571,7 @@ def roofline(launches, F, workload):
     achieved = alg / (ms * 1e-3) / 1e12
     name = launch_kernel_name(kind)
     return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f32"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK["f32"], 4), "traffic": counted_traffic(workload, name),
+            "frac": round(achieved / PEAK["f32"], 4), "traffic": counted_traffic(workload, name, heff_info),
             "kernel": name, "ms_per_launch": round(ms, 3), "algorithmic_flops_per_launch": int(alg),
             "launch_share_of_hpsi_time": round(ms / sum(r[1] for r in launches), 3),
             "useful_mfma_over_F_alg": round(useful / F, 3)}
