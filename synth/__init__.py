@@ -292,16 +292,17 @@ CONFIGS = {
 }
 
 
-# Reduced-M twins of the two largest workloads: the same orbital count,
+# Reduced-M twins of the three largest workloads: the same orbital count,
 # electron count, spin projection and sub-Hamiltonian share, with a bond
 # dimension small enough for the CPU oracle (whose cost grows as K^4 in the
 # number of operator constructions, not with M).  Their stored products are
 # written by tests/golden/make_golden.py.
 TWINS = {
+    "C3T": dict(K=54, n_elec=54, two_sz=0, M=48, seed_base=3100),
     "C4T": dict(K=76, n_elec=113, two_sz=1, M=48, seed_base=4100),
     "C5T": dict(K=108, n_elec=30, two_sz=0, M=48, seed_base=5100, n_proc=16, proc_id=1),
 }
-TWIN_ROOTS = {"C4T": 8, "C5T": 1}
+TWIN_ROOTS = {"C3T": 1, "C4T": 8, "C5T": 1}
 
 
 def config_problem(name: str, **over) -> Problem:

@@ -6,6 +6,8 @@ Hamiltonian) is saved as float64 .npy; for the 8-orbital workload also the
 FCI ground energy (lowest eigenvalue of the determinant-space matrix).
 
 * C1, C2: the full 8-orbital and the 24-orbital M = 500 workloads (scheme CN);
+* C3T: 54 orbitals, 54 electrons, S_z = 0 at M = 48, scheme CN with the middle
+  transform;
 * C4T: 76 orbitals, 113 electrons, S_z = 1/2 at M = 48, eight seeded start
   vectors (the 8-root block), scheme CN with the middle transform;
 * C5T: 108 orbitals, 30 electrons, S_z = 0 at M = 48, sub-Hamiltonian 1 of 16
@@ -29,7 +31,7 @@ import synth  # noqa: E402
 from oracle import blockops, fci, share  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ALL = ("C1", "C2", "C4T", "C5T", "C2E")
+ALL = ("C1", "C2", "C3T", "C4T", "C5T", "C2E")
 
 
 def twin_vectors(p, name):

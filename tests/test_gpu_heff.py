@@ -594,12 +594,13 @@ def test_work_list_independent_of_host_threads(monkeypatch):
         _close(H1, H, L, R, ctx)
 
 
-@pytest.mark.parametrize("name", ["C4T", "C5T"])
+@pytest.mark.parametrize("name", ["C3T", "C4T", "C5T"])
 def test_contract_shape_twins(name):
-    """The two largest workloads' shapes at reduced bond dimension, against the
-    oracle's stored products: 76 orbitals, 113 electrons, S_z = 1/2 (CN +
-    middle transform, the 8 seeded vectors of an 8-root block in one call) and
-    108 orbitals, 30 electrons, the sub-Hamiltonian share 1 of 16 (NC-owned
+    """The three largest workloads' shapes at reduced bond dimension, against
+    the oracle's stored products: 54 orbitals, 54 electrons, S_z = 0 (CN +
+    middle transform); 76 orbitals, 113 electrons, S_z = 1/2 (CN + middle
+    transform, the 8 seeded vectors of an 8-root block in one call) and 108
+    orbitals, 30 electrons, the sub-Hamiltonian share 1 of 16 (NC-owned
     operators).  FP64 <= 1e-12 per vector, FP32 <= 1e-5."""
     import torch
     d = _lib()
