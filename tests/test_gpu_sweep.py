@@ -146,6 +146,14 @@ def test_truncated_sweeps_match_oracle(M):
     _sweep_pair(7, 6, 0, M, 7400, 2)
 
 
+@pytest.mark.parametrize("K,N,tsz,M,seed,n_sweeps", [(10, 10, 0, 40, 7800, 2), (10, 9, 1, 30, 7900, 1)])
+def test_ten_orbital_sweeps_match_oracle(K, N, tsz, M, seed, n_sweeps):
+    """Ten orbitals, M = 40 and 30: blocks of up to 40 rows span three 16-row
+    tiles with a ragged tail, and H_eff reaches a few thousand states; even and
+    odd electron counts."""
+    _sweep_pair(K, N, tsz, M, seed, n_sweeps)
+
+
 def test_two_root_sweep_matches_oracle():
     _sweep_pair(6, 6, 0, 10, 7600, 1, n_roots=2)
 
