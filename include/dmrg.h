@@ -194,7 +194,9 @@ typedef struct {
  *              DMRG_PREC_F32) -- the work list's parameters (the number of
  *              equal-cost chunks heavy tiles are cut into, and the height
  *              from which tiles run on the tall kernel) are chosen by timing
- *              one FP32 product of each candidate, then cached for the shape
+ *              one FP32 product of each candidate (on n_roots vectors at
+ *              once, the batch Davidson's products run on), then cached for
+ *              the shape
  *              (the file named by DMRG_TUNE_CACHE, if set, keeps the cache
  *              across processes).  dmrg_heff_get_info reports the choice.
  *              Without it the list takes the defaults, or DMRG_BALANCE and

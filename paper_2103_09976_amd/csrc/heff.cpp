@@ -1095,11 +1095,14 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
     // on the device, held by H from here on (released with it on any failure)
     dmrg_status st = upload_records(C, base, H->recs, stream);
     if (st != DMRG_OK) return st;
-    const int64_t vreg = C->arena.alloc(H->dim * 4 * 2);
+    // candidates are timed on the vector batch the products run on: n_roots
+    // vectors at once (the partial tiles are sized for that many)
+    const int nr = H->n_roots;
+    const int64_t vreg = C->arena.alloc(H->dim * 4 * 2 * nr);
     if (vreg < 0) return fail(DMRG_E_WORKSPACE, "arena too small for the autotuner's vectors");
     float* x = (float*)(C->arena.base + vreg);
-    float* y = x + H->dim;
-    if (!C->dry) DMRG_HIP(hipMemsetAsync(x, 0, H->dim * 4 * 2, s));
+    float* y = x + H->dim * nr;
+    if (!C->dry) DMRG_HIP(hipMemsetAsync(x, 0, H->dim * 4 * 2 * nr, s));
     hipEvent_t e0, e1;
     DMRG_HIP(hipEventCreate(&e0));
     DMRG_HIP(hipEventCreate(&e1));
@@ -1120,7 +1123,7 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
         return r;
     };
     float margin = 1.f;   // a candidate is kept if faster than margin x the best so far
-    // uploads and (unless dry) times one FP32 product of a candidate
+    // uploads and (unless dry) times one FP32 product (n_roots vectors) of a candidate
     auto trial = [&](const TuneParams& tp) {
         if (st != DMRG_OK) return;
         float best_ms = 0.f;
@@ -1152,13 +1155,14 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
                 b.vstride[dmrgk::kPartialBuf] = w.partial_elems;
                 b.p[2] = x;
                 b.p[3] = y;
+                b.vstride[2] = b.vstride[3] = H->dim;
                 // a warm-up, then the best of two timed runs (one when the
                 // warm-up took over 100 ms)
                 best_ms = 1e30f;
                 int runs = 2;
                 for (int k = -1; k < runs && r == DMRG_OK; ++k) {
                     hipEventRecord(e0, s);
-                    r = run_work_f32(dw, b, 1, stream);
+                    r = run_work_f32(dw, b, nr, stream);
                     hipEventRecord(e1, s);
                     if (r == DMRG_OK && hipEventSynchronize(e1) != hipSuccess) r = fail(DMRG_E_HIP, "autotune timing");
                     float ms = 0.f;

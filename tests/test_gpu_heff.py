@@ -512,29 +512,40 @@ def test_graph_replay_matches_eager():
     _close(G, H, L, R, ctx)
 
 
-def test_autotune_choice_cache_and_parity(monkeypatch, tmp_path):
-    """DMRG_HEFF_AUTOTUNE times every candidate work list and keeps the
-    fastest; the product still matches the oracle; a second H_eff of the same
-    shape takes the cached choice (also from the cache file)."""
+@pytest.mark.parametrize("n_roots", [1, 2])
+def test_autotune_choice_cache_and_parity(monkeypatch, tmp_path, n_roots):
+    """DMRG_HEFF_AUTOTUNE times every candidate work list (on n_roots vectors
+    at once) and keeps the fastest; the product still matches the oracle (with
+    two roots: a batch of psi and 2 psi, against the oracle's product and twice
+    it); a second H_eff of the same shape takes the cached choice (also from
+    the cache file)."""
+    import torch
     d = _lib()
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("DMRG_TUNE_CACHE", str(cache))
     p = synth.make_problem(14, 14, 0, 1000, 82)
     ref = blockops.MiddleHeff(p, "CN").apply(p.psi)
-    ctx, L, R, H, keep = _step(p, arena=8 << 30)
-    T = ctx.heff_create(L, R, 1, d.DMRG_PREC_F32, flags=d.DMRG_HEFF_AUTOTUNE | d.DMRG_HEFF_GRAPH)
+    ctx, L, R, H, keep = _step(p, arena=24 << 30)   # two H_eff, partial tiles for n_roots vectors
+    T = ctx.heff_create(L, R, n_roots, d.DMRG_PREC_F32, flags=d.DMRG_HEFF_AUTOTUNE | d.DMRG_HEFF_GRAPH)
     info = T.info()
-    print(f"[gpu] autotune {info}", flush=True)
+    print(f"[gpu] autotune roots={n_roots} {info}", flush=True)
     assert info["tuned"] == "timed" and len(info["candidates"]) >= 3
     assert all(c["ms_f32"] > 0 for c in info["candidates"])
-    got = _apply(T, p.psi)
-    got32 = _apply(T, p.psi, d.DMRG_PREC_F32)
+    X = np.stack([p.psi * (v + 1) for v in range(n_roots)])
+    got = {}
+    for prec, dt in ((d.DMRG_PREC_F64, torch.float64), (d.DMRG_PREC_F32, torch.float32)):
+        x = torch.from_numpy(X.ravel().copy()).to("cuda:0", dt)
+        y = torch.empty_like(x)
+        T.apply(x, y, prec, n_roots)
+        torch.cuda.synchronize()
+        got[prec] = y.double().cpu().numpy().reshape(n_roots, -1)
     _close(T, H)
-    T2 = ctx.heff_create(L, R, 1, d.DMRG_PREC_F32, flags=d.DMRG_HEFF_AUTOTUNE)
+    T2 = ctx.heff_create(L, R, n_roots, d.DMRG_PREC_F32, flags=d.DMRG_HEFF_AUTOTUNE)
     info2 = T2.info()
     _close(T2, L, R, ctx)
-    assert _rel(got, ref) <= 1e-12
-    assert _rel(got32, ref) <= 1e-5
+    for v in range(n_roots):
+        assert _rel(got[d.DMRG_PREC_F64][v], (v + 1) * ref) <= 1e-12
+        assert _rel(got[d.DMRG_PREC_F32][v], (v + 1) * ref) <= 1e-5
     assert info2["tuned"] == "cached"
     assert (info2["balance_target"], info2["tall_min_rows"]) == (info["balance_target"], info["tall_min_rows"])
     assert cache.read_text().strip()
