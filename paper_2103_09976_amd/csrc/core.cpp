@@ -743,7 +743,7 @@ int64_t work_bytes(const WorkList& w) {
 // Copies the selected parts of a list into one arena region: the tasks and
 // reductions (with_tasks) and the groups and contributions (with_records).
 static dmrg_status upload_parts(Ctx* ctx, const WorkList& w, DevWork& d, void* stream, bool with_tasks,
-                                bool with_records) {
+                                bool with_records, bool with_useful = true) {
     auto round = [](int64_t x) { return (x + 255) & ~int64_t(255); };
     int64_t bytes = 0;
     int64_t toff[dmrgk::kNumClass] = {};
@@ -769,7 +769,8 @@ static dmrg_status upload_parts(Ctx* ctx, const WorkList& w, DevWork& d, void* s
             d.task[c] = (dmrgk::Task*)(base + toff[c]);
             d.ntask[c] = (int)w.task[c].size();
             d.useful[c] = 0;
-            for (const dmrgk::Task& t : w.task[c]) d.useful[c] += task_useful_flops(w, t);
+            if (with_useful)
+                for (const dmrgk::Task& t : w.task[c]) d.useful[c] += task_useful_flops(w, t);
             if (dev && !w.task[c].empty())
                 DMRG_HIP(hipMemcpyAsync(d.task[c], w.task[c].data(), w.task[c].size() * sizeof(dmrgk::Task),
                                         hipMemcpyHostToDevice, s));
@@ -805,8 +806,9 @@ dmrg_status upload_records(Ctx* ctx, const WorkList& w, DevWork& d, void* stream
     return upload_parts(ctx, w, d, stream, false, true);
 }
 
-dmrg_status upload_tasks(Ctx* ctx, const WorkList& w, const DevWork& recs, DevWork& d, void* stream) {
-    const dmrg_status st = upload_parts(ctx, w, d, stream, true, false);
+dmrg_status upload_tasks(Ctx* ctx, const WorkList& w, const DevWork& recs, DevWork& d, void* stream,
+                         bool with_useful) {
+    const dmrg_status st = upload_parts(ctx, w, d, stream, true, false, with_useful);
     d.groups = recs.groups;
     d.contribs = recs.contribs;
     return st;

@@ -256,7 +256,9 @@ dmrg_status upload_work(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
 // groups and contributions those of recs: lists that differ only in their tasks
 // share one copy of the records)
 dmrg_status upload_records(Ctx* ctx, const WorkList& w, DevWork& d, void* stream);
-dmrg_status upload_tasks(Ctx* ctx, const WorkList& w, const DevWork& recs, DevWork& d, void* stream);
+// (with_useful = false leaves DevWork::useful at zero: lists that are only timed)
+dmrg_status upload_tasks(Ctx* ctx, const WorkList& w, const DevWork& recs, DevWork& d, void* stream,
+                         bool with_useful = true);
 int64_t task_bytes(const WorkList& w);   // arena bytes upload_tasks takes
 // arena bytes upload_work takes for a list
 int64_t work_bytes(const WorkList& w);

@@ -1131,7 +1131,7 @@ static dmrg_status autotune(dmrg_heff* H, void* stream) {
         st = with_list(tp, [&](const WorkList& w) -> dmrg_status {
             DevWork dw;
             int64_t preg = -1;
-            dmrg_status r = upload_tasks(C, w, H->recs, dw, stream);
+            dmrg_status r = upload_tasks(C, w, H->recs, dw, stream, false);
             // the partial tiles at the size the chosen list takes (8-byte
             // elements, n_roots vectors): a candidate that does not fit is
             // skipped, unless none has fitted yet
