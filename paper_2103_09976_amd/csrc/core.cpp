@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <tuple>
 
 #include "core.hpp"
@@ -562,9 +563,33 @@ bool records_fit(const WorkList& w, const dmrgk::Task& t) {
 }
 
 void balance_work(WorkList& w, int target_tasks) {
-    double total = 0;
+    // the cost of every group of every task (it depends on the task's rows and
+    // columns), computed on several threads; the sums and the cutting below run
+    // in list order, so the result is the same for any thread count
+    std::vector<const dmrgk::Task*> all;
     for (auto& T : w.task)
-        for (const dmrgk::Task& t : T) total += task_cost(w, t);
+        for (const dmrgk::Task& t : T) all.push_back(&t);
+    std::vector<size_t> goff(all.size() + 1, 0);
+    for (size_t i = 0; i < all.size(); ++i) goff[i + 1] = goff[i] + (size_t)(all[i]->g1 - all[i]->g0);
+    std::vector<double> gcost(goff.back()), tcost(all.size());
+    {
+        const unsigned nth = (unsigned)std::max<size_t>(
+            1, std::min<size_t>({32, std::max(1u, std::thread::hardware_concurrency()), all.size() / 4096 + 1}));
+        std::vector<std::thread> th;
+        for (unsigned k = 0; k < nth; ++k)
+            th.emplace_back([&, k]() {
+                for (size_t i = k; i < all.size(); i += nth) {
+                    const dmrgk::Task& t = *all[i];
+                    double tc = 0;
+                    for (int g = t.g0; g < t.g1; ++g)
+                        tc += gcost[goff[i] + (g - t.g0)] = group_cost(w, w.groups[g], t.m, t.ncol);
+                    tcost[i] = tc;
+                }
+            });
+        for (auto& x : th) x.join();
+    }
+    double total = 0;
+    for (double c : tcost) total += c;
     if (total <= 0 || target_tasks < 1) return;
     // chunks of at least kMinChunkCost: small problems are not cut into pieces
     // whose fixed cost (records, partial tile, reduction) exceeds their work
@@ -572,12 +597,11 @@ void balance_work(WorkList& w, int target_tasks) {
     const double cap = std::max(total / target_tasks, kMinChunkCost);
     std::vector<std::pair<double, dmrgk::Task>> out[dmrgk::kNumClass];
     int64_t poff = w.partial_elems;
-    std::vector<double> gc;
+    size_t ti = 0;
     for (auto& T : w.task) {
         for (const dmrgk::Task& t : T) {
-            gc.resize(t.g1 - t.g0);
-            double tc = 0;
-            for (int g = t.g0; g < t.g1; ++g) tc += gc[g - t.g0] = group_cost(w, w.groups[g], t.m, t.ncol);
+            const double* gc = gcost.data() + goff[ti];
+            const double tc = tcost[ti++];
             const int nchunk = (int)std::min<double>(std::ceil(tc / cap), t.g1 - t.g0);
             if (nchunk <= 1 && records_fit(w, t)) {
                 out[task_class_of(w, t)].emplace_back(tc, t);
